@@ -1,0 +1,122 @@
+/*
+ * gpfo.h -- C interface of the FP64 CPU oracle for the coupled Grand-Potential
+ * phase-field / lattice-Boltzmann time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This oracle is the plain, slow, obviously
+ * correct statement of the discrete method that the HIP library is checked
+ * against.  It shares no code, header, table or helper with the library under
+ * paper_2608_26908_amd/; only tests, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.  Nothing in the product path may call it.
+ *
+ * What it computes (paper sections / equations):
+ *   - phase-field update, Eq. (PhfGrand) with the double-obstacle W of
+ *     Eq. (Wpot) and the Gibbs-simplex constraint (Sec. 2.1);
+ *   - chemical-potential update, Eq. (conc), with the advection term added
+ *     by the paper (Sec. 2.1) and U = 0 in solids;
+ *   - BGK lattice-Boltzmann collide + stream, Eqs. (LBMEq_1), (f^eq),
+ *     (discreteForce), with the drag force G_D and solutal buoyancy G_B
+ *     (Eq. buoyancy), moments Eq. (rhovel); D2Q9 from Table LBM_Schemes,
+ *     D3Q19 (textbook set; the paper's own 3D lattice is D3Q27);
+ *   - staggered order of Algorithm phfLBM (App. A): phi -> mu -> LBM.
+ * Every reading of a silent or garbled passage is listed in the design doc and
+ * restated at the function that implements it in gpfo.cpp.
+ *
+ * Layout of every field array: [component][z][y][x], x fastest, FP64.
+ * Lattice numbering: D2Q9 as in the paper's lattice figure (0 rest, 1 +x,
+ * 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-)); D3Q19: 0 rest,
+ * 1..6 = +x,-x,+y,-y,+z,-z, then (+,+,0),(-,-,0),(+,-,0),(-,+,0),
+ * (+,0,+),(-,0,-),(+,0,-),(-,0,+),(0,+,+),(0,-,-),(0,+,-),(0,-,+).
+ */
+#ifndef GPFO_H
+#define GPFO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { GPFO_OBSTACLE = 0, GPFO_WELL = 1 };
+enum { GPFO_INIT_SEED = 0, GPFO_INIT_LAMELLAE = 1, GPFO_INIT_LIQUID = 2 };
+/* parameters the complex-step derivative can be taken with respect to */
+enum { GPFO_P_DELTA = 0, GPFO_P_TAU = 1, GPFO_P_DIFF = 2, GPFO_P_GBETA = 3,
+       GPFO_P_DIFF1 = 4, GPFO_P_GBETA1 = 5 };
+
+typedef struct {
+  int32_t dim;            /* 2 or 3 */
+  int64_t n[3];           /* cells per axis (n[2] = 1 in 2D) */
+  int32_t periodic[3];    /* 1: periodic axis, 0: walls at both ends */
+  int32_t N;              /* phases, liquid is the last one (2 or 3) */
+  int32_t nc;             /* independent solutes K-1 (1 or 2) */
+  int32_t potential;      /* GPFO_OBSTACLE (paper) or GPFO_WELL (test only) */
+  double dx, dt, eps, tau_pf;
+  double gamma[3][3];     /* interface energies gamma_ab (symmetric) */
+  double delta[3][3];     /* cubic anisotropy strength per pair (symmetric) */
+  double chi[2][2];       /* susceptibility dC/dmu, common to all phases (SPD) */
+  double c0[3][2];        /* C^a(mu) = c0[a] + chi mu */
+  double dS[3];           /* psi^a gets + dS[a] (T - T_E); liquid dS = 0 */
+  double T_E, T_iso;
+  double D[3][2];         /* diffusivity per phase and solute */
+  double G, V, y0;        /* frozen gradient T = T_E + G (x_p - y0 - V n); G = 0: T = T_iso */
+  int32_t pull_axis;
+  double tau_lb, rho0;
+  double gbeta[2];        /* signed g*beta_i */
+  double c_ref[2];
+  int32_t grav_axis, grav_sign;  /* unit gravity vector = grav_sign * e_{grav_axis} */
+  double h_drag, W0;      /* drag kappa = 2 nu h / W0 */
+  double lid_u;           /* test only: top wall of axis 1 moves along axis 0 */
+  int32_t init_kind;
+  double init_center[3], init_radius;
+  double lam_width, lam_height;
+  double mu_inf[2], noise_sigma;
+} gpfo_params;
+
+typedef struct gpfo_sim gpfo_sim;
+
+/* Create a simulation with the initial state of the chosen init kind and
+ * noise drawn from `seed`.  Returns NULL on invalid parameters. */
+gpfo_sim* gpfo_create(const gpfo_params* p, uint64_t seed);
+void gpfo_destroy(gpfo_sim* s);
+void gpfo_set_threads(int nthreads);
+/* Advance n coupled steps. */
+void gpfo_step(gpfo_sim* s, int64_t nsteps);
+int64_t gpfo_step_index(const gpfo_sim* s);
+int64_t gpfo_cells(const gpfo_sim* s);
+int32_t gpfo_Q(const gpfo_sim* s);
+
+/* field ids: 0 phi [N], 1 mu [nc], 2 f [Q], 3 rho [1], 4 U [dim],
+ * 5 C [nc] (mixture composition), 6 T [1], 7 active-set bitmask [1] */
+int64_t gpfo_field_count(const gpfo_sim* s, int32_t field);
+int gpfo_get(const gpfo_sim* s, int32_t field, double* dst);
+int gpfo_set(gpfo_sim* s, int32_t field, const double* src);
+/* totals: 0 solute per component (nc values), 1 mass (1 value) */
+int gpfo_total(const gpfo_sim* s, int32_t which, double* out);
+
+/* Pointwise pieces, exposed for the unit pins. */
+int gpfo_lattice(int32_t dim, int32_t* c_out /* Q*3 */, double* w_out, int32_t* opp_out);
+double gpfo_aniso_ac(int32_t dim, const double* q, double delta);
+double gpfo_aniso_A(int32_t dim, const double* q, double gamma, double delta);
+void gpfo_aniso_dAdq(int32_t dim, const double* q, double gamma, double delta, double* out);
+/* complex-step derivative dA/dq_a of gpfo_aniso_A (step h), the definition
+ * the analytic gradient is pinned to */
+void gpfo_aniso_dAdq_cs(int32_t dim, const double* q, double gamma, double delta,
+                        double h, double* out);
+int gpfo_project(int32_t m, const double* v, double* out);
+void gpfo_interp_h(int32_t N, const double* phi, double* h, double* dh /* N*N, dh[b*N+a] = dh_b/dphi_a */);
+void gpfo_feq(int32_t dim, double rho, const double* u, double* feq);
+void gpfo_guo(int32_t dim, double tau, const double* u, const double* F, double* S);
+double gpfo_normal(uint64_t seed, uint64_t j);
+
+/* Complex-step derivative of L = 1/2 sum (phi_T - target)^2 after nsteps
+ * steps from the state of `s` (left untouched), with respect to parameter
+ * `which` (GPFO_P_*); also returns L. */
+int gpfo_loss_grad_cs(const gpfo_sim* s, int64_t nsteps, const double* target,
+                      int32_t which, double h, double* loss_out, double* grad_out);
+/* Directional derivative of the state after nsteps in the direction of an
+ * initial-state perturbation, by complex step (tangent of the step map). */
+int gpfo_tangent_cs(const gpfo_sim* s, int64_t nsteps, int32_t field, const double* dir,
+                    double h, int32_t out_field, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

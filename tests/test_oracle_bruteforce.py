@@ -1,0 +1,41 @@
+"""Brute force: the oracle against a literal pure-Python evaluator of the
+same discrete step (tests/bruteforce.py) on 8x8 and 4x4x4 random states."""
+import numpy as np
+import pytest
+
+from bruteforce import Step
+from inputs import KINDS, busy_config, random_state
+
+
+def _compare(oracle, cfg, st, steps):
+    sim = oracle.OracleSim(cfg)
+    for k in ("phi", "mu", "f", "u"):
+        sim.set(k, st[k])
+    bf = Step(cfg)
+    s = dict(st, step=0)
+    for _ in range(steps):
+        s = bf.step(s)
+    sim.step(steps)
+    for k in ("phi", "mu", "f", "u"):
+        a, b = sim.get(k), s[k]
+        # U is a small moment of O(0.1) populations: its round-off scales with f
+        scale = max(np.abs(b).max(), np.abs(s["f"]).max() if k == "u" else 0.0, 1e-300)
+        assert np.abs(a - b).max() <= 1e-13 * scale, (k, np.abs(a - b).max(), scale)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_one_step_vs_literal_evaluator(oracle, kind):
+    n = [8, 8] if "2d" in kind else [4, 4, 4]
+    cfg = busy_config(kind, n)
+    _compare(oracle, cfg, random_state(cfg, 11), 1)
+
+
+@pytest.mark.parametrize("kind", ["binary2d", "ternary2d"])
+def test_ten_steps_vs_literal_evaluator(oracle, kind):
+    cfg = busy_config(kind, [8, 8])
+    _compare(oracle, cfg, random_state(cfg, 12), 10)
+
+
+def test_lid_and_well_vs_literal_evaluator(oracle):
+    cfg = busy_config("binary2d", [8, 8], periodic=[0, 0], lid_u=0.05, potential="well")
+    _compare(oracle, cfg, random_state(cfg, 13), 3)
