@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled GP phase-field / lattice-Boltzmann step on one
+MI355X, in MLUPS (million lattice-cell updates per second; one update = one
+cell through one whole coupled step), FP32 and FP64 side by side, with the
+HBM roofline of the dominant kernel and the FP64 CPU oracle as a baseline.
+
+Workload: the 3D binary-alloy dendrite with natural convection, 256^3 cells,
+D3Q19, two phases, one solute, FP32 storage and arithmetic (the
+configuration the HBM-roofline target is stated on); the same grid in FP64
+is timed beside it.  Inputs are synthetic (seed + noise from a fixed seed)
+and resident in HBM before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def bytes_per_lup(cfg, s):
+    """Algorithmic bytes per lattice update: the state read once and written
+    once, phi counted N-1 times (sum phi = 1), U and T derived:
+    2 (N - 1 + nc + Q) s."""
+    Q = 9 if cfg["dim"] == 2 else 19
+    return 2 * (cfg["N"] - 1 + cfg["nc"] + Q) * s
+
+
+def run_gpu(cfg, precision, steps, warmup):
+    import torch
+    from paper_2608_26908_amd.gpf import Sim
+    sim = Sim(cfg, precision=precision)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    t0 = time.perf_counter()
+    # every kernel launch is bracketed by HIP events on the library's stream
+    # (torch's current stream); the call returns summed per-kernel times
+    k_phi_ms, k_mulbm_ms = sim.step_timed(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    cells = sim.cells
+    sol = sim.reduce("solute")
+    sim.close()
+    return dict(ms_per_step=ms / steps, wall_s=wall, cells=cells,
+                k_phi_ms=k_phi_ms / steps, k_mulbm_ms=k_mulbm_ms / steps,
+                mlups=cells * steps / (ms * 1e-3) / 1e6, solute=[float(v) for v in sol])
+
+
+def cpu_baseline(cfg, steps=2):
+    """The FP64 oracle as it stands, on this host's cores, on a bounded
+    sample of the same workload: the full grid, one untimed step, then
+    `steps` timed steps."""
+    from oracle import pyoracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    sim = pyoracle.OracleSim(cfg, threads=threads)
+    sim.step(1)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    cells = 1
+    for a in range(cfg["dim"]):
+        cells *= cfg["n"][a]
+    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full {cfg['n']} grid, FP64 oracle, {steps} timed steps after 1 untimed step "
+                      f"({dt:.1f} s)"}
+
+
+def traffic_record(name, precision):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_mulbm_{name}_{precision}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        from paper_2608_26908_amd.build import source_digest
+        if rec.get("source_digest") != source_digest():
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="dendrite3d")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a device-to-device copy of this many MiB (a kernel of known "
+                         "traffic to calibrate the HBM byte counters of a profiler run)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the single-GPU throughput is the figure reported)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_26908_amd.workloads import workload
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    cfg = workload(args.workload)
+    if args.copy_calib_mib:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: 3 copies of {args.copy_calib_mib} MiB", file=sys.stderr, flush=True)
+        del a, b
+    r32 = run_gpu(cfg, "fp32", args.steps, args.warmup)
+    print(f"# fp32: {r32['mlups']:.1f} MLUPS, {r32['ms_per_step']:.3f} ms/step "
+          f"(k_phi {r32['k_phi_ms']:.3f} ms, k_mulbm {r32['k_mulbm_ms']:.3f} ms)", file=sys.stderr,
+          flush=True)
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_gpu(cfg, "fp64", args.steps, args.warmup)
+        print(f"# fp64: {r64['mlups']:.1f} MLUPS, {r64['ms_per_step']:.3f} ms/step", file=sys.stderr,
+              flush=True)
+
+    b32 = bytes_per_lup(cfg, 4)
+    cells = r32["cells"]
+    achieved = b32 * cells / (r32["k_mulbm_ms"] * 1e-3) / 1e9
+    traffic = traffic_record(args.workload, "fp32")
+    line = {
+        "metric": "MLUPS of coupled PF+LBM step (FP32 vs FP64) + % HBM roofline; adjoint/forward cost",
+        "value": round(r32["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: 3D binary-alloy dendrite with natural convection, "
+                               f"{'x'.join(str(v) for v in cfg['n'])} cells, D3Q19, 2 phases, 1 solute, "
+                               "FP32 storage (f as f - w rho0)",
+                   "grid": cfg["n"], "lattice": "D3Q19", "phases": cfg["N"], "solutes": cfg["nc"],
+                   "precision": "fp32"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_mulbm (chemical potential + LBM collide/stream)",
+                     "bytes_per_lup": b32,
+                     "step_frac": round(b32 * cells / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels_ms": {"k_phi": round(r32["k_phi_ms"], 4), "k_mulbm": round(r32["k_mulbm_ms"], 4)},
+    }
+    if r64:
+        b64 = bytes_per_lup(cfg, 8)
+        line["fp64"] = {"value": round(r64["mlups"], 2), "unit": "MLUPS",
+                        "ms_per_step": round(r64["ms_per_step"], 4),
+                        "k_phi_ms": round(r64["k_phi_ms"], 4), "k_mulbm_ms": round(r64["k_mulbm_ms"], 4),
+                        "roofline_frac": round(b64 * cells / (r64["k_mulbm_ms"] * 1e-3) / 1e9
+                                               / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

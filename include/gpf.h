@@ -1,0 +1,188 @@
+/*
+ * gpf.h -- C ABI of the MI355X (gfx950) library for the coupled
+ * Grand-Potential phase-field / lattice-Boltzmann time step.
+ *
+ * What one step computes (paper sections / equations):
+ *   1. phase fields phi_a by the grand-potential Allen-Cahn equation,
+ *      Eq. (PhfGrand), with the anisotropic gradient energy, the double
+ *      obstacle W of Eq. (Wpot) and the Gibbs-simplex constraint of Sec. 2.1;
+ *   2. chemical potentials mu_i by Eq. (conc): h-interpolated
+ *      susceptibility, the dh/dt source, and advection by the fluid velocity
+ *      (the paper's modification; U = 0 in solids);
+ *   3. one BGK collide + stream, Eq. (LBMEq_1) with f^eq of Eq. (f^eq) and
+ *      the discrete force of Eq. (discreteForce), carrying the solutal
+ *      buoyancy of Eq. (buoyancy) and the drag force G_D that enforces
+ *      no-slip at the diffuse solid-liquid interface;
+ *   4. staggered in the order of Algorithm phfLBM (App. A).
+ * D2Q9 (Table LBM_Schemes) in 2D, D3Q19 in 3D.
+ *
+ * Conventions for every call:
+ *   - Return value: a gpf_status; GPF_OK = 0, negative on error.  No C++
+ *     exception and no abort crosses this boundary.  gpf_last_error()
+ *     returns a message for the last failing call on a context.
+ *   - Field layout (host and device): [component][z][y][x], x fastest,
+ *     cells = n[0] * n[1] * n[2] (n[2] = 1 in 2D).
+ *   - Lattice numbering: D2Q9 as in the paper's lattice figure (0 rest,
+ *     1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-)); D3Q19:
+ *     0 rest, 1..6 = +x,-x,+y,-y,+z,-z, then (+,+,0),(-,-,0),(+,-,0),(-,+,0),
+ *     (+,0,+),(-,0,-),(+,0,-),(-,0,+),(0,+,+),(0,-,-),(0,+,-),(0,-,+).
+ *   - Phases: solids first, liquid last.  n_components = K counts all
+ *     species, so there are nc = K - 1 independent chemical potentials.
+ *   - A context owns its device buffers; every host pointer passed in
+ *     belongs to the caller and is not retained.  A context is used by one
+ *     host thread at a time.
+ */
+#ifndef GPF_H
+#define GPF_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gpf_ctx gpf_ctx;
+
+typedef enum {
+  GPF_OK = 0,
+  GPF_ERR_ARG = -1,         /* NULL pointer, wrong count, unknown enum value */
+  GPF_ERR_PARAM = -2,       /* physically or numerically invalid parameter */
+  GPF_ERR_NOMEM = -3,       /* device allocation failed */
+  GPF_ERR_DEVICE = -4,      /* a HIP call failed (message names it) */
+  GPF_ERR_NONFINITE = -5,   /* health check found NaN/Inf or rho <= 0 */
+  GPF_ERR_STATE = -6,       /* call not valid in the current state */
+  GPF_ERR_UNSUPPORTED = -7  /* valid but not built: (dim, lattice, N, nc) outside the instances */
+} gpf_status;
+
+typedef enum { GPF_D2Q9 = 0, GPF_D3Q19 = 1 } gpf_lattice;
+typedef enum { GPF_FP64 = 0, GPF_FP32 = 1 } gpf_precision;
+typedef enum { GPF_OBSTACLE = 0, GPF_WELL = 1 } gpf_potential;
+typedef enum { GPF_INIT_SEED = 0, GPF_INIT_LAMELLAE = 1, GPF_INIT_LIQUID = 2 } gpf_init_kind;
+
+/* Fields readable with gpf_read / gpf_read_device (components per cell):
+ *   GPF_PHI   N      order parameters phi^n
+ *   GPF_MU    nc     chemical potentials mu^n
+ *   GPF_F     Q      populations f^n after streaming (the full f, also in FP32 mode)
+ *   GPF_RHO   1      sum_k f_k
+ *   GPF_U     dim    lattice velocity of the last collision (advects mu in the next step)
+ *   GPF_C     nc     mixture composition sum_a h_a(phi) C^a(mu)
+ *   GPF_T     1      temperature T(x, n)
+ *   GPF_FLAGS 1      active-phase bitmask (bit a: phase a present in the lattice neighbourhood)
+ *   GPF_FPOST Q      the stored populations: post-collision f*_k - w_k rho0 of the last step,
+ *                    before streaming, exactly as held on the device (checkpoint form)
+ * Writable with gpf_write: GPF_PHI, GPF_MU, GPF_F, GPF_U, GPF_FPOST.  Reading
+ * GPF_PHI, GPF_MU, GPF_U and GPF_FPOST and writing them back is exact in both
+ * precisions, so with gpf_set_step_index a run resumes bitwise. */
+typedef enum {
+  GPF_PHI = 0, GPF_MU = 1, GPF_F = 2, GPF_RHO = 3, GPF_U = 4, GPF_C = 5, GPF_T = 6, GPF_FLAGS = 7,
+  GPF_FPOST = 8
+} gpf_field;
+
+typedef enum { GPF_SUM_SOLUTE = 0, GPF_SUM_MASS = 1 } gpf_reduction;
+
+typedef struct {
+  int32_t dim;            /* 2 or 3 */
+  int64_t n[3];           /* cells per axis; n[2] ignored in 2D */
+  double dx;              /* phase-field grid spacing (the LBM runs in lattice units) */
+  uint32_t periodic_mask; /* bit a set: axis a periodic, else zero-flux / no-slip walls */
+} gpf_grid;
+
+typedef struct {
+  int32_t lattice;        /* gpf_lattice; must match dim */
+  int32_t precision;      /* gpf_precision: FP64, or FP32 storage and arithmetic */
+  int32_t potential;      /* gpf_potential: OBSTACLE (the paper) or WELL (test only) */
+  double dt, eps, tau_pf; /* time step, interface parameter eps, relaxation tau of Eq. (PhfGrand) */
+  double gamma[3][3];     /* interface energies gamma_ab, symmetric */
+  double delta[3][3];     /* cubic anisotropy strength per pair, symmetric */
+  double chi[2][2];       /* susceptibility, SPD, common to all phases: C^a = c0[a] + chi mu */
+  double c0[3][2];
+  double dS[3];           /* grand potential psi^a gets + dS[a] (T - T_E) */
+  double T_E, T_iso;      /* eutectic / equilibrium temperature; temperature when G = 0 */
+  double D[3][2];         /* diffusivity per phase and solute (solids 0 in the paper) */
+  double G, V, y0;        /* frozen gradient T = T_E + G (x_pull - y0 - V n), V in cells/step */
+  int32_t pull_axis;
+  double tau_lb, rho0;    /* BGK relaxation time (> 1/2) and reference density */
+  double gbeta[2];        /* signed products g * beta_i of Eq. (buoyancy) */
+  double c_ref[2];        /* reference liquid composition of Eq. (buoyancy) */
+  int32_t grav_axis, grav_sign; /* unit gravity vector = grav_sign * e_{grav_axis} */
+  double h_drag, W0;      /* drag kappa = 2 nu h / W0 of G_D, nu = (tau_lb - 1/2)/3 */
+  double lid_u;           /* test only: upper wall of axis 1 moves along axis 0 (cavity) */
+  int32_t init_kind;      /* gpf_init_kind */
+  double init_center[3], init_radius; /* seed centre (cell units, cell i at coordinate i), radius */
+  double lam_width, lam_height;       /* lamella width along x, solid height along pull_axis */
+  double mu_inf[2], noise_sigma;      /* mu^0_i = mu_inf_i + sigma z(seed, cell, i) */
+  int64_t health_every;   /* > 0: check NaN/Inf and rho <= 0 every so many steps and at the
+                             end of each gpf_step call (the call then synchronises); 0: never */
+  void* (*dev_alloc)(size_t bytes, void* user); /* NULL: hipMalloc; else e.g. torch's caching allocator */
+  void (*dev_free)(void* ptr, void* user);
+  void* alloc_user;
+} gpf_params;
+
+/* Create a simulation and its initial state (paper's problem statement:
+ * grid, phases, components, material parameters; App. A Algorithm phfLBM
+ * "Initialization").  Initial state: phi^0 from the 1D equilibrium profile
+ * of the double obstacle, 1/2 - 1/2 sin(4 s / (pi eps)) for |s| <= pi^2 eps/8,
+ * around a seed (circle/sphere) or a flat front of alternating lamellae;
+ * mu^0 = mu_inf + noise_sigma * z with z standard normal from a
+ * counter-based SplitMix64 + Box-Muller stream keyed by `seed`
+ * (z index = cell * nc + i); f^0 = w_k rho0; U = 0.
+ * n_phases: 2 or 3.  n_components: 2 or 3 (nc = n_components - 1).
+ * Errors: GPF_ERR_ARG (NULL), GPF_ERR_PARAM (tau_lb <= 1/2, dt, dx, eps,
+ * tau_pf <= 0, explicit stability bound exceeded, chi not SPD, axes out of
+ * range, lattice/dim mismatch), GPF_ERR_UNSUPPORTED (N, nc, dim outside the
+ * built instances), GPF_ERR_NOMEM, GPF_ERR_DEVICE.  On error *out = NULL. */
+int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_components,
+             const gpf_params* params, uint64_t seed);
+
+/* Launch subsequent work on this HIP stream (a hipStream_t, e.g. torch's
+ * current stream); NULL selects the null stream.  The stream is not owned. */
+int gpf_set_stream(gpf_ctx* ctx, void* hip_stream);
+
+/* Advance n >= 0 coupled steps (Algorithm phfLBM, one pass per step).
+ * Asynchronous unless health_every > 0, in which case the call waits for
+ * its last health check and returns GPF_ERR_NONFINITE (with the first
+ * failing step in the message) when it failed. */
+int gpf_step(gpf_ctx* ctx, int64_t n);
+
+/* Like gpf_step, and records HIP events around every kernel launch on the
+ * context's stream; kernel_ms[j] receives the summed milliseconds of kernel
+ * j of the step (j = 0: phase field, 1: chemical potential + LBM), count
+ * up to n_kernels.  Synchronises.  For measurement only. */
+int gpf_step_timed(gpf_ctx* ctx, int64_t n, double* kernel_ms, int32_t n_kernels);
+
+/* Copy a field to caller-owned host memory as FP64 (adds w_k rho0 back to f
+ * in every precision).  count must equal components * cells.  Synchronises. */
+int gpf_read(gpf_ctx* ctx, int32_t field, double* host_dst, size_t count);
+
+/* Copy a field to caller-owned device memory in the context's precision
+ * (double or float; f as the full f).  bytes must equal components * cells *
+ * element size.  Asynchronous on the context's stream. */
+int gpf_read_device(gpf_ctx* ctx, int32_t field, void* dev_dst, size_t bytes);
+
+/* Overwrite a state field from FP64 host memory (GPF_PHI, GPF_MU, GPF_F as
+ * the post-streaming f^n, GPF_U as the velocity of the previous step).
+ * Synchronises.  Used by tests to inject states. */
+int gpf_write(gpf_ctx* ctx, int32_t field, const double* host_src, size_t count);
+
+/* FP64 totals in a fixed summation order (deterministic): GPF_SUM_SOLUTE
+ * writes nc values sum_cells sum_a h_a C^a_i(mu); GPF_SUM_MASS one value
+ * sum_cells sum_k f_k.  Synchronises. */
+int gpf_reduce(gpf_ctx* ctx, int32_t which, double* out);
+
+/* Change one scalar parameter between steps: "delta" (all anisotropic
+ * pairs), "tau_pf", "D" / "D1" (liquid diffusivity of solute 0 / 1),
+ * "gbeta" / "gbeta1".  Re-validated like gpf_init. */
+int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
+
+/* Step counter n (it sets the time of the pulled temperature field).  The
+ * setter is for resuming a checkpoint; n >= 0. */
+int64_t gpf_step_index(const gpf_ctx* ctx);
+int gpf_set_step_index(gpf_ctx* ctx, int64_t n);
+const char* gpf_last_error(const gpf_ctx* ctx);
+const char* gpf_status_string(int status);
+void gpf_destroy(gpf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,164 @@
+// gpf_device.hpp -- device-side building blocks of the coupled GP
+// phase-field / lattice-Boltzmann step for gfx950: lattice tables, the
+// per-launch parameter block and the pointwise model functions.
+//
+// Storage precision R is float or double; arithmetic is carried out in R.
+// Every field is structure-of-arrays [component][z][y][x], x fastest.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpf {
+
+// ---------------------------------------------------------------------------
+// Lattices.  D2Q9 numbering of the paper's lattice figure with the weights of
+// Table LBM_Schemes; D3Q19 is the textbook 19-velocity set (the paper's own
+// 3D lattice is D3Q27).  The neighbourhood a cell update reads is the same
+// set of offsets, so one table serves the stencils and the streaming.
+// ---------------------------------------------------------------------------
+template <int D> struct Lat;
+
+template <> struct Lat<2> {
+  static constexpr int Q = 9;
+  __host__ __device__ static constexpr int c(int k, int a) {
+    constexpr int t[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+                             {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    return t[k][a];
+  }
+  __host__ __device__ static constexpr int opp(int k) {
+    constexpr int t[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    return t[k];
+  }
+  __host__ __device__ static constexpr double w(int k) {
+    return k == 0 ? 4.0 / 9.0 : (k <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+
+template <> struct Lat<3> {
+  static constexpr int Q = 19;
+  __host__ __device__ static constexpr int c(int k, int a) {
+    constexpr int t[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                              {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                              {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                              {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    return t[k][a];
+  }
+  __host__ __device__ static constexpr int opp(int k) {
+    constexpr int t[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    return t[k];
+  }
+  __host__ __device__ static constexpr double w(int k) {
+    return k == 0 ? 1.0 / 3.0 : (k <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Parameters of one launch, passed by value (kernel arguments).
+// ---------------------------------------------------------------------------
+template <class R> struct KP {
+  int n[3];
+  int per[3];
+  int64_t sy, sz, cells;  // strides of y and z, number of cells
+  int potential;          // 0 obstacle, 1 well
+  int pull_axis, grav_axis;
+  R dx, dt, eps, rate;    // rate = dt / (tau_pf eps)
+  R gamma[3][3], delta[3][3];
+  R chi[2][2], c0[3][2], dS[3];
+  R D[3][2];
+  R G, tdev_iso, T_E;     // T - T_E = G (x_pull - shift) if G != 0, else tdev_iso
+  R tau_lb, rho0, gbeta[2], c_ref[2], grav_sign, kappa, lid_u;
+  R qmin2;                // |q|^2 below which the anisotropy direction is undefined
+  R w[19];                // lattice weights in R
+};
+
+// ---------------------------------------------------------------------------
+// Pointwise model functions.
+// ---------------------------------------------------------------------------
+
+// dA/dq of the pair energy A(q) = gamma a_c(q)^2 |q|^2 with the cubic
+// anisotropy a_c = 1 - delta (3 - 4 sum q_a^4 / |q|^4) (2D: 1 + delta cos 4theta):
+//   dA/dq = 2 gamma a_c (a_c q + |q|^2 grad a_c),
+//   grad a_c = 16 delta (q_a^3 / |q|^4 - q_a sum q^4 / |q|^6);
+// a_c = 1 and grad a_c = 0 below |q|^2 = qmin2.
+template <int D, class R>
+__device__ __forceinline__ void dAdq(const R (&q)[D], R gamma, R delta, R qmin2, R (&out)[D]) {
+  R q2 = R(0), q4 = R(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    R s = q[a] * q[a];
+    q2 += s;
+    q4 += s * s;
+  }
+  if (!(q2 > qmin2)) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) out[a] = R(2) * gamma * q[a];
+    return;
+  }
+  R inv = R(1) / q2;
+  R inv2 = inv * inv;
+  R ac = R(1) - delta * (R(3) - R(4) * q4 * inv2);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    R g = R(16) * delta * inv2 * (q[a] * q[a] * q[a] - q[a] * q4 * inv);
+    out[a] = R(2) * gamma * ac * (ac * q[a] + q2 * g);
+  }
+}
+
+// Interpolation h_a(phi): N = 2: phi^2 (3 - 2 phi); N = 3 adds 2 phi_0 phi_1 phi_2.
+template <int N, class R>
+__device__ __forceinline__ void interp_h(const R (&ph)[N], R (&h)[N]) {
+  R tri = (N == 3) ? R(2) * ph[0] * ph[1] * ph[N - 1] : R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) h[b] = ph[b] * ph[b] * (R(3) - R(2) * ph[b]) + tri;
+}
+
+// dh_b / dphi_a, a fixed.
+template <int N, class R>
+__device__ __forceinline__ R dh(const R (&ph)[N], int b, int a) {
+  R r = (a == b) ? R(6) * ph[b] * (R(1) - ph[b]) : R(0);
+  if (N == 3) {
+    R other = R(1);
+#pragma unroll
+    for (int g = 0; g < N; ++g)
+      if (g != a) other *= ph[g];
+    r += R(2) * other;
+  }
+  return r;
+}
+
+// Euclidean projection of v[0..m) onto the simplex {sum = 1, >= 0}
+// (sort descending, largest j with u_j - (sum_{i<=j} u_i - 1)/j > 0;
+// Held, Wolfe and Crowder 1974).  m <= 3: a three-element sorting network.
+template <class R>
+__device__ __forceinline__ void project_simplex(int m, R (&v)[3], R (&out)[3]) {
+  R u0 = v[0], u1 = (m > 1) ? v[1] : R(0), u2 = (m > 2) ? v[2] : R(0);
+  if (m > 1 && u1 > u0) { R t = u0; u0 = u1; u1 = t; }
+  if (m > 2) {
+    if (u2 > u1) { R t = u1; u1 = u2; u2 = t; }
+    if (u1 > u0) { R t = u0; u0 = u1; u1 = t; }
+  }
+  R csum = u0, theta = u0 - R(1);  // j = 1 always qualifies: u0 - (u0 - 1) = 1 > 0
+  if (m > 1) {
+    csum += u1;
+    R t = (csum - R(1)) / R(2);
+    if (u1 - t > R(0)) theta = t;
+  }
+  if (m > 2) {
+    csum += u2;
+    R t = (csum - R(1)) / R(3);
+    if (u2 - t > R(0)) theta = t;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[i] = (i < m && v[i] - theta > R(0)) ? v[i] - theta : R(0);
+}
+
+// Neighbour coordinate along one axis for field values: periodic axes wrap,
+// walls mirror the adjacent cell (zero normal derivative).
+__device__ __forceinline__ int nb_field(int x, int s, int n, int per) {
+  int y = x + s;
+  if (y < 0) y = per ? y + n : 0;
+  if (y >= n) y = per ? y - n : n - 1;
+  return y;
+}
+
+}  // namespace gpf

@@ -1,0 +1,605 @@
+// gpf_kernels.hpp -- HIP kernels of the coupled GP phase-field / LBM step.
+//
+// One step = two launches on a 64 x 4 (x, y) block grid, z on blockIdx.z:
+//   k_phi    phi^n, mu^n            -> phi^{n+1}          (Eq. PhfGrand, Sec. 2.1)
+//   k_mulbm  phi^n, phi^{n+1}, mu^n, U^{n-1}, f*^{n-1}
+//                                   -> mu^{n+1}, U^n, f*^n (Eq. conc; Eqs. LBMEq_1,
+//                                      f^eq, discreteForce, buoyancy, rhovel)
+// f buffers hold post-collision, pre-streaming populations as deviations
+// f - w_k rho0; streaming is a pull at the start of k_mulbm, with half-way
+// bounce-back where the source lies behind a wall.  All buffers are A-B:
+// every kernel reads one copy and writes the other.
+#pragma once
+#include "gpf_device.hpp"
+
+namespace gpf {
+
+constexpr int BX = 64;
+constexpr int BY = 4;
+
+// Population k of f^n at cell (x, y, z) = P, as a deviation from w_k rho0:
+// pulled from the stored post-collision f* of the upstream cell P - c_k, or,
+// when that cell lies behind a wall, the reflected f*_{opp k}(P) (half-way
+// bounce-back; the wall sits on the zero-flux face of phi and mu).  The
+// test-only moving upper wall of axis 1 adds 6 w_k rho0 c_k . U_wall.
+template <int D, class R>
+__device__ __forceinline__ R pull_f(const KP<R>& p, const R* __restrict__ fin, int x, int y, int z,
+                                    int64_t P, int k) {
+  using L = Lat<D>;
+  int src[3] = {x - L::c(k, 0), y - L::c(k, 1), z - L::c(k, 2)};
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (L::c(k, a) == 0) continue;
+    if (src[a] < 0 || src[a] >= p.n[a]) {
+      if (p.per[a])
+        src[a] = (src[a] + p.n[a]) % p.n[a];
+      else
+        in = false;
+    }
+  }
+  if (in) return fin[k * p.cells + (int64_t)src[2] * p.sz + (int64_t)src[1] * p.sy + src[0]];
+  R val = fin[Lat<D>::opp(k) * p.cells + P];
+  if (L::c(k, 1) < 0 && !p.per[1] && y - L::c(k, 1) >= p.n[1])
+    val += R(6) * p.w[k] * p.rho0 * R(L::c(k, 0)) * p.lid_u;
+  return val;
+}
+
+// ---------------------------------------------------------------------------
+// Phase field: active set, right-hand side, projection.
+// ---------------------------------------------------------------------------
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(BX * BY)
+k_phi(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
+      R tshift) {
+  const int x = blockIdx.x * BX + threadIdx.x;
+  const int y = blockIdx.y * BY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= p.n[0] || y >= p.n[1]) return;
+  const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
+
+  // neighbour coordinates (wall: mirror, periodic: wrap)
+  int xs[3], ys[3], zs[3];
+#pragma unroll
+  for (int s = -1; s <= 1; ++s) {
+    xs[s + 1] = nb_field(x, s, p.n[0], p.per[0]);
+    ys[s + 1] = nb_field(y, s, p.n[1], p.per[1]);
+    zs[s + 1] = (D == 3) ? nb_field(z, s, p.n[2], p.per[2]) : 0;
+  }
+  // the 9 (2D) / 19 (3D) point neighbourhood: offsets with at most two
+  // non-zero components; corners of the 3x3x3 cube are never touched
+  R v[N][3][3][3];
+  unsigned active = 0u;
+#pragma unroll
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (dx != 0 && dy != 0 && dz != 0) continue;
+        const int64_t j = (int64_t)zs[dz + 1] * p.sz + (int64_t)ys[dy + 1] * p.sy + xs[dx + 1];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          R val = phi[b * p.cells + j];
+          v[b][dz + 1][dy + 1][dx + 1] = val;
+          if (val > R(0)) active |= 1u << b;
+        }
+      }
+
+  const int na = __builtin_popcount(active);
+  if (na <= 1) {  // bulk: phi unchanged
+#pragma unroll
+    for (int b = 0; b < N; ++b) phi_out[b * p.cells + P] = v[b][1][1][1];
+    return;
+  }
+
+  const int pos[3] = {x, y, z};
+  const R idx = R(1) / p.dx;
+  const R ih2 = R(0.5) / p.dx;
+  // central difference along e at X = P + o (o within the neighbourhood)
+  auto gc = [&](int b, int ox, int oy, int oz, int e) -> R {
+    int op[3] = {ox, oy, oz}, om[3] = {ox, oy, oz};
+    op[e] += 1;
+    om[e] -= 1;
+    return (v[b][op[2] + 1][op[1] + 1][op[0] + 1] - v[b][om[2] + 1][om[1] + 1][om[0] + 1]) * ih2;
+  };
+
+  R div[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) div[b] = R(0);
+
+  // face fluxes J_a = -sum_b phi_b,f dA_ab/dq(q_ab,f), q = phi_a grad phi_b - phi_b grad phi_a
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+#pragma unroll
+    for (int s = -1; s <= 1; s += 2) {
+      const bool wall = !p.per[a] && ((s < 0 && pos[a] == 0) || (s > 0 && pos[a] == p.n[a] - 1));
+      if (wall) continue;
+      int o[3] = {0, 0, 0};
+      o[a] = s;
+      R pf[N], gf[N][D];
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const R vP = v[b][1][1][1];
+        const R vQ = v[b][o[2] + 1][o[1] + 1][o[0] + 1];
+        pf[b] = R(0.5) * (vP + vQ);
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+          if (e == a)
+            gf[b][e] = R(s) * (vQ - vP) * idx;
+          else
+            gf[b][e] = R(0.5) * (gc(b, 0, 0, 0, e) + gc(b, o[0], o[1], o[2], e));
+        }
+      }
+      R J[N];
+#pragma unroll
+      for (int b = 0; b < N; ++b) J[b] = R(0);
+#pragma unroll
+      for (int al = 0; al < N; ++al)
+#pragma unroll
+        for (int be = al + 1; be < N; ++be) {
+          R q[D], g[D];
+#pragma unroll
+          for (int e = 0; e < D; ++e) q[e] = pf[al] * gf[be][e] - pf[be] * gf[al][e];
+          dAdq<D, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, g);
+          J[al] -= pf[be] * g[a];
+          J[be] += pf[al] * g[a];
+        }
+#pragma unroll
+      for (int b = 0; b < N; ++b) div[b] += R(s) * J[b] * idx;
+    }
+  }
+
+  // cell-centre terms
+  R ph[N], g0[N][D];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    ph[b] = v[b][1][1][1];
+#pragma unroll
+    for (int e = 0; e < D; ++e) g0[b][e] = gc(b, 0, 0, 0, e);
+  }
+  R cell[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) cell[b] = R(0);
+#pragma unroll
+  for (int al = 0; al < N; ++al)
+#pragma unroll
+    for (int be = al + 1; be < N; ++be) {
+      R q[D], g[D];
+#pragma unroll
+      for (int e = 0; e < D; ++e) q[e] = ph[al] * g0[be][e] - ph[be] * g0[al][e];
+      dAdq<D, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, g);
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        cell[al] += g[e] * g0[be][e];
+        cell[be] -= g[e] * g0[al][e];
+      }
+    }
+
+  // grand potentials psi^b(mu, T) = -1/2 mu.chi.mu - mu.c0[b] + dS[b] (T - T_E)
+  R m[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) m[i] = mu[i * p.cells + P];
+  const R tdev = (p.G != R(0)) ? p.G * (R(pos[p.pull_axis]) - tshift) : p.tdev_iso;
+  R ps[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    R r = R(0);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      R chimu = R(0);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) chimu += p.chi[i][j] * m[j];
+      r += -R(0.5) * m[i] * chimu - m[i] * p.c0[b][i];
+    }
+    ps[b] = r + p.dS[b] * tdev;
+  }
+
+  R vv[3] = {R(0), R(0), R(0)};
+  int which[3] = {0, 0, 0};
+  int cnt = 0;
+#pragma unroll
+  for (int al = 0; al < N; ++al) {
+    R dW = R(0);
+#pragma unroll
+    for (int be = 0; be < N; ++be) {
+      if (be == al) continue;
+      if (p.potential == 0)
+        dW += R(1.6211389382774044) * p.gamma[al][be] * ph[be];  // 16 / pi^2
+      else
+        dW += R(18) * p.gamma[al][be] * ph[al] * ph[be] * ph[be];
+    }
+    R drive = R(0);
+#pragma unroll
+    for (int be = 0; be < N; ++be) drive += ps[be] * dh<N, R>(ph, be, al);
+    const R Ra = p.eps * (div[al] - cell[al]) - dW / p.eps - drive;
+    if ((active >> al) & 1u) {
+      vv[cnt] = ph[al] + p.rate * Ra;
+      which[cnt] = al;
+      ++cnt;
+    }
+  }
+  R out[3];
+  project_simplex<R>(cnt, vv, out);
+  R res[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) res[b] = R(0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (j < cnt) {
+#pragma unroll
+      for (int b = 0; b < N; ++b)
+        if (which[j] == b) res[b] = out[j];
+    }
+#pragma unroll
+  for (int b = 0; b < N; ++b) phi_out[b * p.cells + P] = res[b];
+}
+
+// ---------------------------------------------------------------------------
+// Chemical potential + lattice Boltzmann (forces, moments, BGK + Guo, pull
+// streaming).
+// ---------------------------------------------------------------------------
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(BX * BY)
+k_mulbm(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
+        const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
+        R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout) {
+  using L = Lat<D>;
+  const int x = blockIdx.x * BX + threadIdx.x;
+  const int y = blockIdx.y * BY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= p.n[0] || y >= p.n[1]) return;
+  const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
+  const int pos[3] = {x, y, z};
+  const int64_t stride[3] = {1, p.sy, p.sz};
+
+  // per-cell quantities at phi^{n+1}: h, c* = sum h C(mu^n), M = sum phi D chi
+  auto quant = [&](int64_t j, R (&M)[NC][NC], R (&cs)[NC], R (&m)[NC]) {
+    R ph[N], h[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) ph[b] = phi1[b * p.cells + j];
+    interp_h<N, R>(ph, h);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) m[i] = mu[i * p.cells + j];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      cs[i] = R(0);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) M[i][k] = R(0);
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        R C = p.c0[b][i];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) C += p.chi[i][k] * m[k];
+        cs[i] += h[b] * C;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) M[i][k] += ph[b] * p.D[b][i] * p.chi[i][k];
+      }
+    }
+  };
+
+  R MP[NC][NC], cP[NC], mP[NC];
+  quant(P, MP, cP, mP);
+  R divJ[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) divJ[i] = R(0);
+  const R conv = p.dx / p.dt;  // lattice velocity -> phase-field units
+  const R idx = R(1) / p.dx;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const R uP = uold[a * p.cells + P];
+#pragma unroll
+    for (int s = -1; s <= 1; s += 2) {
+      const bool wall = !p.per[a] && ((s < 0 && pos[a] == 0) || (s > 0 && pos[a] == p.n[a] - 1));
+      if (wall) continue;
+      const int q = nb_field(pos[a], s, p.n[a], p.per[a]);
+      const int64_t Qj = P + (int64_t)(q - pos[a]) * stride[a];
+      R MQ[NC][NC], cQ[NC], mQ[NC];
+      quant(Qj, MQ, cQ, mQ);
+      const R uf = R(0.5) * (uP + uold[a * p.cells + Qj]) * conv;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        R JD = R(0);
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+          JD += -R(0.5) * (MP[i][k] + MQ[i][k]) * (R(s) * (mQ[k] - mP[k]) * idx);
+        const R JA = uf * R(0.5) * (cP[i] + cQ[i]);
+        divJ[i] += R(s) * (JD + JA) * idx;
+      }
+    }
+  }
+  R ph0[N], ph1[N], h0[N], h1[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    ph0[b] = phi0[b * p.cells + P];
+    ph1[b] = phi1[b * p.cells + P];
+  }
+  interp_h<N, R>(ph0, h0);
+  interp_h<N, R>(ph1, h1);
+  R Dl[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) Dl[i] = -p.dt * divJ[i];
+  R sh = R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    sh += h1[b];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      R C = p.c0[b][i];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mP[k];
+      Dl[i] -= C * (h1[b] - h0[b]);
+    }
+  }
+  R mn[NC];
+  if (NC == 1) {
+    mn[0] = mP[0] + Dl[0] / (sh * p.chi[0][0]);
+  } else {
+    const R a11 = sh * p.chi[0][0], a12 = sh * p.chi[0][1];
+    const R a21 = sh * p.chi[1][0], a22 = sh * p.chi[1][NC - 1];
+    const R det = a11 * a22 - a12 * a21;
+    mn[0] = mP[0] + (a22 * Dl[0] - a12 * Dl[NC - 1]) / det;
+    mn[NC - 1] = mP[NC - 1] + (-a21 * Dl[0] + a11 * Dl[NC - 1]) / det;
+  }
+#pragma unroll
+  for (int i = 0; i < NC; ++i) mu_out[i * p.cells + P] = mn[i];
+
+  // ---- LBM: pull streaming of the previous post-collision populations ----
+  R f[L::Q];
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) f[k] = pull_f<D, R>(p, fin, x, y, z, P, k);
+  // moments (deviation storage: rho = rho0 + sum f~, momentum = sum f~ c)
+  R dr = R(0), mom[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) mom[a] = R(0);
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    dr += f[k];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      if (L::c(k, a) != 0) mom[a] += R(L::c(k, a)) * f[k];
+  }
+  const R rho = p.rho0 + dr;
+  const R phil = ph1[N - 1];
+  R bsum = R(0);
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    R Cl = p.c0[N - 1][i];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) Cl += p.chi[i][k] * mn[k];
+    bsum += p.gbeta[i] * (Cl - p.c_ref[i]);
+  }
+  R FB[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) FB[a] = R(0);
+  FB[p.grav_axis] = -rho * phil * bsum * p.grav_sign;
+  const R sol = (R(1) - phil) * (R(1) - phil);
+  R u[D], F[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    u[a] = (phil != R(0)) ? (mom[a] + R(0.5) * FB[a]) / (rho * (R(1) + R(0.5) * p.kappa * sol))
+                          : R(0);
+    F[a] = FB[a] - p.kappa * rho * sol * u[a];
+  }
+  R uu = R(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) uu += u[a] * u[a];
+  const R pref = R(1) - R(0.5) / p.tau_lb;
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    R cu = R(0), cF = R(0), uF = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (L::c(k, a) != 0) {
+        cu += R(L::c(k, a)) * u[a];
+        cF += R(L::c(k, a)) * F[a];
+      }
+      uF += u[a] * F[a];
+    }
+    const R feq = p.w[k] * (dr + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+    const R S = pref * p.w[k] * (R(3) * (cF - uF) + R(9) * cu * cF);
+    fout[k * p.cells + P] = f[k] - (f[k] - feq) / p.tau_lb + S;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) u_out[a * p.cells + P] = u[a];
+}
+
+// ---------------------------------------------------------------------------
+// Auxiliary kernels (read, write, totals, health).  One thread per cell on a
+// 1D grid.
+// ---------------------------------------------------------------------------
+
+// f^n_k(P) = stored f*_k(P - c_k) (+ bounce-back), plus w_k rho0: the full f.
+template <int D, class R>
+__global__ void k_gather_f(KP<R> p, const R* __restrict__ fin, double* __restrict__ out) {
+  using L = Lat<D>;
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= p.cells) return;
+  const int x = (int)(P % p.n[0]);
+  const int y = (int)((P / p.sy) % p.n[1]);
+  const int z = (int)(P / p.sz);
+  for (int k = 0; k < L::Q; ++k)
+    out[k * p.cells + P] = (double)pull_f<D, R>(p, fin, x, y, z, P, k) + L::w(k) * (double)p.rho0;
+}
+
+// inverse of k_gather_f: the stored pre-streaming f* that streams to f^n
+template <int D, class R>
+__global__ void k_scatter_f(KP<R> p, const double* __restrict__ fn, R* __restrict__ fst) {
+  using L = Lat<D>;
+  const int64_t Qc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (Qc >= p.cells) return;
+  const int x = (int)(Qc % p.n[0]);
+  const int y = (int)((Qc / p.sy) % p.n[1]);
+  const int z = (int)(Qc / p.sz);
+  for (int k = 0; k < L::Q; ++k) {
+    int dst[3] = {x + L::c(k, 0), y + L::c(k, 1), z + L::c(k, 2)};
+    bool in = true;
+    for (int a = 0; a < D; ++a)
+      if (dst[a] < 0 || dst[a] >= p.n[a]) {
+        if (p.per[a])
+          dst[a] = (dst[a] + p.n[a]) % p.n[a];
+        else
+          in = false;
+      }
+    double val;
+    if (in) {
+      val = fn[k * p.cells + (int64_t)dst[2] * p.sz + (int64_t)dst[1] * p.sy + dst[0]] - L::w(k) * (double)p.rho0;
+    } else {
+      const int kb = L::opp(k);
+      val = fn[kb * p.cells + Qc] - L::w(kb) * (double)p.rho0;
+      if (L::c(kb, 1) < 0 && !p.per[1] && y - L::c(kb, 1) >= p.n[1])
+        val -= 6.0 * L::w(kb) * (double)p.rho0 * L::c(kb, 0) * (double)p.lid_u;
+    }
+    fst[k * p.cells + Qc] = (R)val;
+  }
+}
+
+template <class R>
+__global__ void k_to_double(const R* __restrict__ in, double* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
+template <class R>
+__global__ void k_from_double(const double* __restrict__ in, R* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (R)in[i];
+}
+
+// derived per-cell fields in FP64: 0 rho, 1 mixture composition C (nc comps),
+// 2 temperature, 3 active-set bitmask
+template <int D, int N, int NC, class R>
+__global__ void k_derived(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ mu,
+                          const double* __restrict__ fgathered, double tshift_d,
+                          double* __restrict__ out) {
+  using L = Lat<D>;
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= p.cells) return;
+  const int x = (int)(P % p.n[0]);
+  const int y = (int)((P / p.sy) % p.n[1]);
+  const int z = (int)(P / p.sz);
+  if (which == 0) {
+    double r = 0.0;
+    for (int k = 0; k < L::Q; ++k) r += fgathered[k * p.cells + P];
+    out[P] = r;
+  } else if (which == 1) {
+    double ph[N], h[N], m[NC];
+    for (int b = 0; b < N; ++b) ph[b] = (double)phi[b * p.cells + P];
+    for (int i = 0; i < NC; ++i) m[i] = (double)mu[i * p.cells + P];
+    interp_h<N, double>(ph, h);
+    for (int i = 0; i < NC; ++i) {
+      double c = 0.0;
+      for (int b = 0; b < N; ++b) {
+        double C = (double)p.c0[b][i];
+        for (int k = 0; k < NC; ++k) C += (double)p.chi[i][k] * m[k];
+        c += h[b] * C;
+      }
+      out[i * p.cells + P] = c;
+    }
+  } else if (which == 2) {
+    const int pos[3] = {x, y, z};
+    out[P] = (double)p.T_E + ((p.G != R(0)) ? (double)p.G * ((double)pos[p.pull_axis] - tshift_d)
+                                              : (double)p.tdev_iso);
+  } else {
+    unsigned mask = 0u;
+    for (int k = 0; k < L::Q; ++k) {
+      const int xx = nb_field(x, L::c(k, 0), p.n[0], p.per[0]);
+      const int yy = nb_field(y, L::c(k, 1), p.n[1], p.per[1]);
+      const int zz = (D == 3) ? nb_field(z, L::c(k, 2), p.n[2], p.per[2]) : 0;
+      const int64_t j = (int64_t)zz * p.sz + (int64_t)yy * p.sy + xx;
+      for (int b = 0; b < N; ++b)
+        if (phi[b * p.cells + j] > R(0)) mask |= 1u << b;
+    }
+    out[P] = (double)mask;
+  }
+}
+
+// FP64 block partial sums in a fixed order: solute (NC values) or mass.
+constexpr int RED_BLOCK = 256;
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(RED_BLOCK)
+k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ mu,
+          const R* __restrict__ f, double* __restrict__ partial) {
+  using L = Lat<D>;
+  __shared__ double sh[NC][RED_BLOCK];
+  const int t = threadIdx.x;
+  double acc[NC];
+  for (int i = 0; i < NC; ++i) acc[i] = 0.0;
+  for (int64_t P = (int64_t)blockIdx.x * RED_BLOCK + t; P < p.cells;
+       P += (int64_t)gridDim.x * RED_BLOCK) {
+    if (which == 0) {
+      double ph[N], h[N], m[NC];
+      for (int b = 0; b < N; ++b) ph[b] = (double)phi[b * p.cells + P];
+      for (int i = 0; i < NC; ++i) m[i] = (double)mu[i * p.cells + P];
+      interp_h<N, double>(ph, h);
+      for (int i = 0; i < NC; ++i) {
+        double c = 0.0;
+        for (int b = 0; b < N; ++b) {
+          double C = (double)p.c0[b][i];
+          for (int k = 0; k < NC; ++k) C += (double)p.chi[i][k] * m[k];
+          c += h[b] * C;
+        }
+        acc[i] += c;
+      }
+    } else {
+      const int x = (int)(P % p.n[0]);
+      const int y = (int)((P / p.sy) % p.n[1]);
+      const int z = (int)(P / p.sz);
+      double r = 0.0;
+      for (int k = 0; k < L::Q; ++k)
+        r += (double)pull_f<D, R>(p, f, x, y, z, P, k) + L::w(k) * (double)p.rho0;
+      acc[0] += r;
+    }
+  }
+  for (int i = 0; i < NC; ++i) sh[i][t] = acc[i];
+  __syncthreads();
+  for (int s = RED_BLOCK / 2; s > 0; s >>= 1) {
+    if (t < s)
+      for (int i = 0; i < NC; ++i) sh[i][t] += sh[i][t + s];
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int i = 0; i < NC; ++i) partial[blockIdx.x * NC + i] = sh[i][0];
+}
+
+__global__ void k_final_sum(const double* __restrict__ partial, int nblocks, int ncomp,
+                            double* __restrict__ out) {
+  __shared__ double sh[RED_BLOCK];
+  for (int i = 0; i < ncomp; ++i) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += RED_BLOCK) acc += partial[b * ncomp + i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = RED_BLOCK / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sh[0];
+    __syncthreads();
+  }
+}
+
+// health: NaN/Inf in phi or mu, or rho <= 0, records the smallest step seen
+template <int D, int N, int NC, class R>
+__global__ void k_health(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu,
+                         const R* __restrict__ f, unsigned long long step,
+                         unsigned long long* __restrict__ bad_step) {
+  using L = Lat<D>;
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= p.cells) return;
+  const int x = (int)(P % p.n[0]);
+  const int y = (int)((P / p.sy) % p.n[1]);
+  const int z = (int)(P / p.sz);
+  bool bad = false;
+  for (int b = 0; b < N; ++b) bad |= !isfinite(phi[b * p.cells + P]);
+  for (int i = 0; i < NC; ++i) bad |= !isfinite(mu[i * p.cells + P]);
+  R r = p.rho0;
+  for (int k = 0; k < L::Q; ++k) r += pull_f<D, R>(p, f, x, y, z, P, k);
+  bad |= !(r > R(0));
+  if (bad) atomicMin(bad_step, step);
+}
+
+}  // namespace gpf

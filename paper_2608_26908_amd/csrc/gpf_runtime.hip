@@ -1,0 +1,729 @@
+// gpf_runtime.hip -- host runtime and C ABI (include/gpf.h) of the coupled
+// GP phase-field / lattice-Boltzmann step on gfx950.
+//
+// Context = validated parameters + A-B device buffers of the state
+// (phi [N], mu [nc], U [dim], f* [Q], structure-of-arrays, x fastest) +
+// the stream work is launched on.  Kernels are instantiated per
+// (dim, N, nc, precision); gpf_init picks one and keeps its launchers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gpf.h"
+#include "gpf_kernels.hpp"
+
+namespace {
+
+// message of the last gpf_init that failed on this thread (no context exists then)
+thread_local std::string g_init_error;
+
+const double kPi = 3.14159265358979323846;
+
+struct Ops;
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct gpf_ctx {
+  gpf_grid grid;
+  gpf_params prm;
+  int N = 0, nc = 0, Q = 0, dim = 0;
+  int64_t n[3] = {1, 1, 1};
+  int64_t cells = 0;
+  size_t esize = 8;  // bytes per stored value
+  hipStream_t stream = nullptr;
+  DevBuf phi[2], mu[2], u[2], f[2];
+  int cur = 0;  // index of the buffers holding step `step`
+  int64_t step = 0;
+  DevBuf scratch;   // FP64 staging for read / write (components * cells doubles)
+  DevBuf partial;   // reduction partials
+  DevBuf redout;    // final reduction values
+  DevBuf badstep;   // health: smallest failing step
+  const Ops* ops = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int fail(gpf_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                         \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, GPF_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+int dev_alloc(gpf_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  if (c->prm.dev_alloc) {
+    p = c->prm.dev_alloc(bytes, c->prm.alloc_user);
+    if (!p) return fail(c, GPF_ERR_NOMEM, "dev_alloc callback returned NULL for %zu bytes", bytes);
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+      return fail(c, GPF_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  b.ptr = p;
+  b.bytes = bytes;
+  return GPF_OK;
+}
+
+void dev_release(gpf_ctx* c, DevBuf& b) {
+  if (!b.ptr) return;
+  if (c->prm.dev_alloc) {
+    if (c->prm.dev_free) c->prm.dev_free(b.ptr, c->prm.alloc_user);
+  } else {
+    (void)hipFree(b.ptr);
+  }
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// kernel parameter block
+// ---------------------------------------------------------------------------
+template <class R>
+gpf::KP<R> make_kp(const gpf_ctx* c) {
+  const gpf_params& p = c->prm;
+  gpf::KP<R> k;
+  std::memset(&k, 0, sizeof(k));
+  for (int a = 0; a < 3; ++a) {
+    k.n[a] = (int)c->n[a];
+    k.per[a] = (a < c->dim) ? (int)((c->grid.periodic_mask >> a) & 1u) : 1;
+  }
+  k.sy = c->n[0];
+  k.sz = c->n[0] * c->n[1];
+  k.cells = c->cells;
+  k.potential = p.potential;
+  k.pull_axis = p.pull_axis;
+  k.grav_axis = p.grav_axis;
+  k.dx = (R)c->grid.dx;
+  k.dt = (R)p.dt;
+  k.eps = (R)p.eps;
+  k.rate = (R)(p.dt / (p.tau_pf * p.eps));
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      k.gamma[a][b] = (R)p.gamma[a][b];
+      k.delta[a][b] = (R)p.delta[a][b];
+    }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) k.chi[i][j] = (R)p.chi[i][j];
+  for (int a = 0; a < 3; ++a) {
+    for (int i = 0; i < 2; ++i) {
+      k.c0[a][i] = (R)p.c0[a][i];
+      k.D[a][i] = (R)p.D[a][i];
+    }
+    k.dS[a] = (R)p.dS[a];
+  }
+  k.G = (R)p.G;
+  k.tdev_iso = (R)(p.T_iso - p.T_E);
+  k.T_E = (R)p.T_E;
+  k.tau_lb = (R)p.tau_lb;
+  k.rho0 = (R)p.rho0;
+  for (int i = 0; i < 2; ++i) {
+    k.gbeta[i] = (R)p.gbeta[i];
+    k.c_ref[i] = (R)p.c_ref[i];
+  }
+  k.grav_sign = (R)p.grav_sign;
+  const double nu = (p.tau_lb - 0.5) / 3.0;
+  k.kappa = (R)(2.0 * nu * p.h_drag / p.W0);
+  k.lid_u = (R)p.lid_u;
+  k.qmin2 = (sizeof(R) == 8) ? (R)1e-24 : (R)1e-12;
+  for (int q = 0; q < c->Q; ++q)
+    k.w[q] = (R)((c->dim == 2) ? gpf::Lat<2>::w(q) : gpf::Lat<3>::w(q));
+  return k;
+}
+
+// the pulled temperature's moving origin y0 + V n
+double tshift(const gpf_ctx* c, int64_t step) { return c->prm.y0 + c->prm.V * (double)step; }
+
+// ---------------------------------------------------------------------------
+// per-instance launchers
+// ---------------------------------------------------------------------------
+struct Ops {
+  int (*step)(gpf_ctx*, int64_t, double*, int);
+  int (*read)(gpf_ctx*, int, double*);  // to scratch (device FP64), returns components
+  int (*write)(gpf_ctx*, int);          // from scratch
+  int (*reduce)(gpf_ctx*, int, double*);
+  int (*read_native)(gpf_ctx*, int, void*);
+};
+
+inline dim3 step_grid(const gpf_ctx* c) {
+  return dim3((unsigned)((c->n[0] + gpf::BX - 1) / gpf::BX), (unsigned)((c->n[1] + gpf::BY - 1) / gpf::BY),
+              (unsigned)c->n[2]);
+}
+inline unsigned lin_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int D, int N, int NC, class R>
+struct Impl {
+  static R* P(DevBuf& b) { return static_cast<R*>(b.ptr); }
+
+  static int health(gpf_ctx* c) {
+    gpf::KP<R> k = make_kp<R>(c);
+    const int s = c->cur;
+    hipLaunchKernelGGL((gpf::k_health<D, N, NC, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0,
+                       c->stream, k, P(c->phi[s]), P(c->mu[s]), P(c->f[s]),
+                       (unsigned long long)c->step,
+                       static_cast<unsigned long long*>(c->badstep.ptr));
+    HIP_OR_FAIL(c, hipGetLastError());
+    return GPF_OK;
+  }
+
+  static int step(gpf_ctx* c, int64_t nsteps, double* kernel_ms, int nk) {
+    gpf::KP<R> k = make_kp<R>(c);
+    const dim3 grid = step_grid(c), block(gpf::BX, gpf::BY, 1);
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (kernel_ms) {
+      for (int i = 0; i < 3; ++i) HIP_OR_FAIL(c, hipEventCreate(&ev[i]));
+      for (int i = 0; i < nk; ++i) kernel_ms[i] = 0.0;
+    }
+    const int64_t H = c->prm.health_every;
+    for (int64_t it = 0; it < nsteps; ++it) {
+      const int s = c->cur, t = 1 - c->cur;
+      const R ts = (R)tshift(c, c->step);
+      if (kernel_ms) HIP_OR_FAIL(c, hipEventRecord(ev[0], c->stream));
+      hipLaunchKernelGGL((gpf::k_phi<D, N, NC, R>), grid, block, 0, c->stream, k, P(c->phi[s]),
+                         P(c->mu[s]), P(c->phi[t]), ts);
+      if (kernel_ms) HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
+      hipLaunchKernelGGL((gpf::k_mulbm<D, N, NC, R>), grid, block, 0, c->stream, k, P(c->phi[s]),
+                         P(c->phi[t]), P(c->mu[s]), P(c->u[s]), P(c->f[s]), P(c->mu[t]),
+                         P(c->u[t]), P(c->f[t]));
+      if (kernel_ms) {
+        HIP_OR_FAIL(c, hipEventRecord(ev[2], c->stream));
+        HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
+        float a = 0.f, b = 0.f;
+        HIP_OR_FAIL(c, hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIP_OR_FAIL(c, hipEventElapsedTime(&b, ev[1], ev[2]));
+        if (nk > 0) kernel_ms[0] += a;
+        if (nk > 1) kernel_ms[1] += b;
+      }
+      HIP_OR_FAIL(c, hipGetLastError());
+      c->cur = t;
+      c->step += 1;
+      if (H > 0 && (c->step % H == 0 || it == nsteps - 1)) {
+        int rc = health(c);
+        if (rc) return rc;
+      }
+    }
+    if (kernel_ms)
+      for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+    return GPF_OK;
+  }
+
+  // field -> scratch (FP64 on the device); returns the component count
+  static int read(gpf_ctx* c, int field, double* comps) {
+    gpf::KP<R> k = make_kp<R>(c);
+    const int s = c->cur;
+    double* out = static_cast<double*>(c->scratch.ptr);
+    const unsigned nb = lin_blocks(c->cells, 256);
+    int ncomp = 0;
+    switch (field) {
+      case GPF_PHI: ncomp = N; break;
+      case GPF_MU: ncomp = NC; break;
+      case GPF_U: ncomp = D; break;
+      default: break;
+    }
+    if (ncomp) {
+      const R* src = field == GPF_PHI ? P(c->phi[s]) : field == GPF_MU ? P(c->mu[s]) : P(c->u[s]);
+      const int64_t cnt = ncomp * c->cells;
+      hipLaunchKernelGGL((gpf::k_to_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, src,
+                         out, cnt);
+    } else if (field == GPF_FPOST) {
+      ncomp = gpf::Lat<D>::Q;
+      const int64_t cnt = ncomp * c->cells;
+      hipLaunchKernelGGL((gpf::k_to_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream,
+                         P(c->f[s]), out, cnt);
+    } else if (field == GPF_F || field == GPF_RHO) {
+      ncomp = (field == GPF_F) ? gpf::Lat<D>::Q : 1;
+      hipLaunchKernelGGL((gpf::k_gather_f<D, R>), dim3(nb), dim3(256), 0, c->stream, k, P(c->f[s]),
+                         out);
+      if (field == GPF_RHO) {
+        // rho into the slot after the Q populations, then move to the front
+        double* rho = out + (int64_t)gpf::Lat<D>::Q * c->cells;
+        hipLaunchKernelGGL((gpf::k_derived<D, N, NC, R>), dim3(nb), dim3(256), 0, c->stream, k, 0,
+                           P(c->phi[s]), P(c->mu[s]), out, 0.0, rho);
+        HIP_OR_FAIL(c, hipMemcpyAsync(out, rho, c->cells * sizeof(double), hipMemcpyDeviceToDevice,
+                                      c->stream));
+      }
+    } else if (field == GPF_C || field == GPF_T || field == GPF_FLAGS) {
+      const int which = field == GPF_C ? 1 : field == GPF_T ? 2 : 3;
+      ncomp = field == GPF_C ? NC : 1;
+      hipLaunchKernelGGL((gpf::k_derived<D, N, NC, R>), dim3(nb), dim3(256), 0, c->stream, k, which,
+                         P(c->phi[s]), P(c->mu[s]), out, tshift(c, c->step), out);
+    } else {
+      return fail(c, GPF_ERR_ARG, "unknown field %d", field);
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
+    *comps = ncomp;
+    return GPF_OK;
+  }
+
+  static int read_native(gpf_ctx* c, int field, void* dst) {
+    const int s = c->cur;
+    size_t bytes = 0;
+    const void* src = nullptr;
+    switch (field) {
+      case GPF_PHI: src = c->phi[s].ptr; bytes = N * c->cells * sizeof(R); break;
+      case GPF_MU: src = c->mu[s].ptr; bytes = NC * c->cells * sizeof(R); break;
+      case GPF_U: src = c->u[s].ptr; bytes = D * c->cells * sizeof(R); break;
+      case GPF_F: {
+        double comps = 0;
+        int rc = read(c, GPF_F, &comps);
+        if (rc) return rc;
+        const int64_t cnt = gpf::Lat<D>::Q * c->cells;
+        hipLaunchKernelGGL((gpf::k_from_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0,
+                           c->stream, static_cast<const double*>(c->scratch.ptr), static_cast<R*>(dst), cnt);
+        HIP_OR_FAIL(c, hipGetLastError());
+        return GPF_OK;
+      }
+      default: return fail(c, GPF_ERR_ARG, "field %d has no native device copy", field);
+    }
+    HIP_OR_FAIL(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return GPF_OK;
+  }
+
+  // scratch (FP64) -> field of the current buffers
+  static int write(gpf_ctx* c, int field) {
+    gpf::KP<R> k = make_kp<R>(c);
+    const int s = c->cur;
+    const double* in = static_cast<const double*>(c->scratch.ptr);
+    if (field == GPF_FPOST) {
+      const int64_t cnt = gpf::Lat<D>::Q * c->cells;
+      hipLaunchKernelGGL((gpf::k_from_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, in,
+                         P(c->f[s]), cnt);
+    } else if (field == GPF_F) {
+      hipLaunchKernelGGL((gpf::k_scatter_f<D, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0,
+                         c->stream, k, in, P(c->f[s]));
+    } else {
+      int ncomp = field == GPF_PHI ? N : field == GPF_MU ? NC : D;
+      R* dst = field == GPF_PHI ? P(c->phi[s]) : field == GPF_MU ? P(c->mu[s]) : P(c->u[s]);
+      const int64_t cnt = ncomp * c->cells;
+      hipLaunchKernelGGL((gpf::k_from_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, in,
+                         dst, cnt);
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
+    return GPF_OK;
+  }
+
+  static int reduce(gpf_ctx* c, int which, double* host_out) {
+    gpf::KP<R> k = make_kp<R>(c);
+    const int s = c->cur;
+    const int nblk = (int)std::min<int64_t>(2048, lin_blocks(c->cells, gpf::RED_BLOCK));
+    const int ncomp = which == GPF_SUM_SOLUTE ? NC : 1;
+    hipLaunchKernelGGL((gpf::k_partial<D, N, NC, R>), dim3(nblk), dim3(gpf::RED_BLOCK), 0, c->stream, k,
+                       which == GPF_SUM_SOLUTE ? 0 : 1, P(c->phi[s]), P(c->mu[s]), P(c->f[s]),
+                       static_cast<double*>(c->partial.ptr));
+    hipLaunchKernelGGL(gpf::k_final_sum, dim3(1), dim3(gpf::RED_BLOCK), 0, c->stream,
+                       static_cast<const double*>(c->partial.ptr), nblk, ncomp,
+                       static_cast<double*>(c->redout.ptr));
+    HIP_OR_FAIL(c, hipGetLastError());
+    HIP_OR_FAIL(c, hipMemcpyAsync(host_out, c->redout.ptr, ncomp * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return GPF_OK;
+  }
+
+  static const Ops* ops() {
+    static const Ops o = {&step, &read, &write, &reduce, &read_native};
+    return &o;
+  }
+};
+
+template <int D, int N, class R>
+const Ops* pick_nc(int nc) {
+  return nc == 1 ? Impl<D, N, 1, R>::ops() : Impl<D, N, 2, R>::ops();
+}
+template <int D, class R>
+const Ops* pick_n(int N, int nc) {
+  return N == 2 ? pick_nc<D, 2, R>(nc) : pick_nc<D, 3, R>(nc);
+}
+template <class R>
+const Ops* pick_d(int dim, int N, int nc) {
+  return dim == 2 ? pick_n<2, R>(N, nc) : pick_n<3, R>(N, nc);
+}
+const Ops* pick(int dim, int N, int nc, int prec) {
+  return prec == GPF_FP64 ? pick_d<double>(dim, N, nc) : pick_d<float>(dim, N, nc);
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+int validate(gpf_ctx* c, const gpf_grid* g, int N, int K, const gpf_params* p) {
+  if (g->dim != 2 && g->dim != 3) return fail(c, GPF_ERR_UNSUPPORTED, "dim must be 2 or 3, got %d", g->dim);
+  if ((g->dim == 2 && p->lattice != GPF_D2Q9) || (g->dim == 3 && p->lattice != GPF_D3Q19))
+    return fail(c, GPF_ERR_PARAM, "lattice %d does not match dim %d (D2Q9 in 2D, D3Q19 in 3D)",
+                p->lattice, g->dim);
+  if (N < 2 || N > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_phases must be 2 or 3, got %d", N);
+  if (K < 2 || K > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_components must be 2 or 3, got %d", K);
+  if (p->precision != GPF_FP64 && p->precision != GPF_FP32)
+    return fail(c, GPF_ERR_ARG, "unknown precision %d", p->precision);
+  if (p->potential != GPF_OBSTACLE && p->potential != GPF_WELL)
+    return fail(c, GPF_ERR_ARG, "unknown potential %d", p->potential);
+  for (int a = 0; a < g->dim; ++a)
+    if (g->n[a] < 1 || g->n[a] > (1 << 20)) return fail(c, GPF_ERR_PARAM, "n[%d] = %lld out of range", a, (long long)g->n[a]);
+  if (g->dim == 3 && g->n[2] > 65535) return fail(c, GPF_ERR_PARAM, "n[2] above 65535");
+  if (!(g->dx > 0)) return fail(c, GPF_ERR_PARAM, "dx must be > 0");
+  if (!(p->dt > 0) || !(p->eps > 0) || !(p->tau_pf > 0))
+    return fail(c, GPF_ERR_PARAM, "dt, eps and tau_pf must be > 0");
+  if (!(p->tau_lb > 0.5)) return fail(c, GPF_ERR_PARAM, "tau_lb must exceed 1/2 (got %g)", p->tau_lb);
+  if (!(p->rho0 > 0)) return fail(c, GPF_ERR_PARAM, "rho0 must be > 0");
+  if (!(p->W0 > 0) || !(p->h_drag >= 0)) return fail(c, GPF_ERR_PARAM, "W0 > 0 and h_drag >= 0 required");
+  const int nc = K - 1;
+  if (nc == 1) {
+    if (!(p->chi[0][0] > 0)) return fail(c, GPF_ERR_PARAM, "chi must be positive");
+  } else {
+    const double det = p->chi[0][0] * p->chi[1][1] - p->chi[0][1] * p->chi[1][0];
+    if (!(p->chi[0][0] > 0) || !(det > 0) || p->chi[0][1] != p->chi[1][0])
+      return fail(c, GPF_ERR_PARAM, "chi must be symmetric positive definite");
+  }
+  if (p->pull_axis < 0 || p->pull_axis >= g->dim || p->grav_axis < 0 || p->grav_axis >= g->dim)
+    return fail(c, GPF_ERR_PARAM, "pull_axis / grav_axis out of range");
+  if (p->grav_sign != 1 && p->grav_sign != -1) return fail(c, GPF_ERR_PARAM, "grav_sign must be +1 or -1");
+  // explicit (forward Euler) stability of the two diffusive updates
+  const double lim = 1.0 / (2.0 * g->dim);
+  double dmax = 0, gmax = 0, dlt = 0;
+  for (int a = 0; a < N; ++a)
+    for (int i = 0; i < nc; ++i) dmax = std::fmax(dmax, p->D[a][i]);
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      if (a == b) continue;
+      gmax = std::fmax(gmax, p->gamma[a][b]);
+      dlt = std::fmax(dlt, std::fabs(p->delta[a][b]));
+      if (p->gamma[a][b] != p->gamma[b][a] || p->delta[a][b] != p->delta[b][a])
+        return fail(c, GPF_ERR_PARAM, "gamma and delta must be symmetric");
+      if (!(p->gamma[a][b] > 0)) return fail(c, GPF_ERR_PARAM, "gamma must be > 0");
+    }
+  if (dmax * p->dt / (g->dx * g->dx) > lim)
+    return fail(c, GPF_ERR_PARAM, "D dt / dx^2 = %g exceeds the explicit bound %g", dmax * p->dt / (g->dx * g->dx), lim);
+  const double pf = gmax * (1 + 3 * dlt) * (1 + 3 * dlt) * p->dt / (p->tau_pf * g->dx * g->dx);
+  if (pf > lim) return fail(c, GPF_ERR_PARAM, "gamma dt / (tau dx^2) = %g exceeds the explicit bound %g", pf, lim);
+  if (dlt >= 1.0 / 15.0) return fail(c, GPF_ERR_PARAM, "|delta| >= 1/15 makes the cubic stiffness negative");
+  if (p->health_every < 0) return fail(c, GPF_ERR_PARAM, "health_every must be >= 0");
+  if ((p->dev_alloc == nullptr) != (p->dev_free == nullptr))
+    return fail(c, GPF_ERR_ARG, "dev_alloc and dev_free must be given together");
+  return GPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// initial state on the host (FP64), written through the same path as gpf_write
+// ---------------------------------------------------------------------------
+
+// counter-based SplitMix64 (Steele, Lea and Flood 2014): output j of the
+// stream keyed by seed is the mix of seed + (j + 1) * golden gamma
+uint64_t mix64(uint64_t seed, uint64_t j) {
+  uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// standard normal number j: Box-Muller on the 53-bit uniforms of counters 2j, 2j+1
+double gauss(uint64_t seed, uint64_t j) {
+  const double u1 = ((double)(mix64(seed, 2 * j) >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(mix64(seed, 2 * j + 1) >> 11) * 0x1.0p-53;
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * kPi * u2);
+}
+// solid fraction of the double-obstacle equilibrium profile at signed distance s
+double solid_fraction(double s, double eps) {
+  const double half = kPi * kPi * eps / 8.0;
+  if (s <= -half) return 1.0;
+  if (s >= half) return 0.0;
+  return 0.5 - 0.5 * std::sin(4.0 * s / (kPi * eps));
+}
+
+int write_host(gpf_ctx* c, int field, const double* src, size_t count);
+
+int init_state(gpf_ctx* c, uint64_t seed) {
+  const gpf_params& p = c->prm;
+  const int64_t cells = c->cells;
+  std::vector<double> phi((size_t)c->N * cells, 0.0), mu((size_t)c->nc * cells, 0.0),
+      f((size_t)c->Q * cells, 0.0), u((size_t)c->dim * cells, 0.0);
+  const double dx = c->grid.dx;
+  for (int64_t P = 0; P < cells; ++P) {
+    const int64_t x[3] = {P % c->n[0], (P / c->n[0]) % c->n[1], P / (c->n[0] * c->n[1])};
+    double sol = 0.0;
+    int solid = 0;
+    if (p.init_kind == GPF_INIT_SEED) {
+      double r2 = 0.0;
+      for (int a = 0; a < c->dim; ++a) {
+        const double d = ((double)x[a] - p.init_center[a]) * dx;
+        r2 += d * d;
+      }
+      sol = solid_fraction(std::sqrt(r2) - p.init_radius * dx, p.eps);
+    } else if (p.init_kind == GPF_INIT_LAMELLAE) {
+      sol = solid_fraction(((double)x[p.pull_axis] - p.lam_height) * dx, p.eps);
+      if (c->N == 3 && p.lam_width > 0) solid = (int)(((int64_t)std::floor((double)x[0] / p.lam_width)) % 2);
+    }
+    phi[(size_t)solid * cells + P] = sol;
+    phi[(size_t)(c->N - 1) * cells + P] = 1.0 - sol;
+    for (int i = 0; i < c->nc; ++i)
+      mu[(size_t)i * cells + P] = p.mu_inf[i] + p.noise_sigma * gauss(seed, (uint64_t)P * c->nc + i);
+    for (int k = 0; k < c->Q; ++k)
+      f[(size_t)k * cells + P] = ((c->dim == 2) ? gpf::Lat<2>::w(k) : gpf::Lat<3>::w(k)) * p.rho0;
+  }
+  int rc;
+  if ((rc = write_host(c, GPF_PHI, phi.data(), phi.size()))) return rc;
+  if ((rc = write_host(c, GPF_MU, mu.data(), mu.size()))) return rc;
+  if ((rc = write_host(c, GPF_F, f.data(), f.size()))) return rc;
+  if ((rc = write_host(c, GPF_U, u.data(), u.size()))) return rc;
+  return GPF_OK;
+}
+
+int components(const gpf_ctx* c, int field) {
+  switch (field) {
+    case GPF_PHI: return c->N;
+    case GPF_MU: return c->nc;
+    case GPF_F: return c->Q;
+    case GPF_RHO: return 1;
+    case GPF_U: return c->dim;
+    case GPF_C: return c->nc;
+    case GPF_T: return 1;
+    case GPF_FLAGS: return 1;
+    case GPF_FPOST: return c->Q;
+  }
+  return -1;
+}
+
+int write_host(gpf_ctx* c, int field, const double* src, size_t count) {
+  if (field != GPF_PHI && field != GPF_MU && field != GPF_F && field != GPF_U && field != GPF_FPOST)
+    return fail(c, GPF_ERR_ARG, "field %d is not writable", field);
+  const size_t want = (size_t)components(c, field) * (size_t)c->cells;
+  if (count != want) return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, want);
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->scratch.ptr, src, want * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  int rc = c->ops->write(c, field);
+  if (rc) return rc;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return GPF_OK;
+}
+
+void free_all(gpf_ctx* c) {
+  for (int s = 0; s < 2; ++s) {
+    dev_release(c, c->phi[s]);
+    dev_release(c, c->mu[s]);
+    dev_release(c, c->u[s]);
+    dev_release(c, c->f[s]);
+  }
+  dev_release(c, c->scratch);
+  dev_release(c, c->partial);
+  dev_release(c, c->redout);
+  dev_release(c, c->badstep);
+}
+
+int set_named(gpf_ctx* c, gpf_params& p, const char* name, double v) {
+  const int l = c->N - 1;
+  if (!std::strcmp(name, "delta")) {
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        if (p.delta[a][b] != 0.0) p.delta[a][b] = v;
+  } else if (!std::strcmp(name, "tau_pf")) {
+    p.tau_pf = v;
+  } else if (!std::strcmp(name, "D")) {
+    p.D[l][0] = v;
+  } else if (!std::strcmp(name, "D1")) {
+    p.D[l][1] = v;
+  } else if (!std::strcmp(name, "gbeta")) {
+    p.gbeta[0] = v;
+  } else if (!std::strcmp(name, "gbeta1")) {
+    p.gbeta[1] = v;
+  } else {
+    return fail(c, GPF_ERR_ARG, "unknown parameter '%s'", name);
+  }
+  return GPF_OK;
+}
+
+}  // namespace
+
+// ============================ C ABI ==========================================
+
+extern "C" {
+
+int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_components,
+             const gpf_params* params, uint64_t seed) {
+  if (!out) return GPF_ERR_ARG;
+  *out = nullptr;
+  if (!grid || !params) return GPF_ERR_ARG;
+  gpf_ctx* c = new (std::nothrow) gpf_ctx;
+  if (!c) return GPF_ERR_NOMEM;
+  int rc = validate(c, grid, n_phases, n_components, params);
+  if (rc) {
+    g_init_error = c->err;
+    delete c;
+    return rc;
+  }
+  c->grid = *grid;
+  c->prm = *params;
+  c->dim = grid->dim;
+  c->N = n_phases;
+  c->nc = n_components - 1;
+  c->Q = (c->dim == 2) ? 9 : 19;
+  for (int a = 0; a < 3; ++a) c->n[a] = (a < c->dim) ? grid->n[a] : 1;
+  c->cells = c->n[0] * c->n[1] * c->n[2];
+  c->esize = (params->precision == GPF_FP64) ? 8 : 4;
+  c->ops = pick(c->dim, c->N, c->nc, params->precision);
+  const size_t cs = (size_t)c->cells * c->esize;
+  for (int s = 0; s < 2 && !rc; ++s) {
+    if (!rc) rc = dev_alloc(c, c->phi[s], c->N * cs);
+    if (!rc) rc = dev_alloc(c, c->mu[s], c->nc * cs);
+    if (!rc) rc = dev_alloc(c, c->u[s], c->dim * cs);
+    if (!rc) rc = dev_alloc(c, c->f[s], c->Q * cs);
+  }
+  if (!rc) rc = dev_alloc(c, c->scratch, (size_t)(c->Q + 1) * c->cells * sizeof(double));
+  if (!rc) rc = dev_alloc(c, c->partial, 2048 * 2 * sizeof(double));
+  if (!rc) rc = dev_alloc(c, c->redout, 4 * sizeof(double));
+  if (!rc) rc = dev_alloc(c, c->badstep, sizeof(unsigned long long));
+  if (!rc) {
+    hipError_t e = hipMemsetAsync(c->badstep.ptr, 0xff, sizeof(unsigned long long), c->stream);
+    if (e != hipSuccess) rc = fail(c, GPF_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
+  }
+  if (!rc) rc = init_state(c, seed);
+  if (rc) {
+    g_init_error = c->err;
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  g_init_error.clear();
+  *out = c;
+  return GPF_OK;
+}
+
+int gpf_set_stream(gpf_ctx* c, void* s) {
+  if (!c) return GPF_ERR_ARG;
+  c->stream = static_cast<hipStream_t>(s);
+  return GPF_OK;
+}
+
+static int check_health_result(gpf_ctx* c) {
+  unsigned long long bad = 0;
+  HIP_OR_FAIL(c, hipMemcpyAsync(&bad, c->badstep.ptr, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (bad != ~0ull)
+    return fail(c, GPF_ERR_NONFINITE, "non-finite phi/mu or rho <= 0 detected at step %llu", bad);
+  return GPF_OK;
+}
+
+int gpf_step(gpf_ctx* c, int64_t n) {
+  if (!c) return GPF_ERR_ARG;
+  if (n < 0) return fail(c, GPF_ERR_ARG, "negative step count");
+  int rc = c->ops->step(c, n, nullptr, 0);
+  if (rc) return rc;
+  if (c->prm.health_every > 0) return check_health_result(c);
+  return GPF_OK;
+}
+
+int gpf_step_timed(gpf_ctx* c, int64_t n, double* kernel_ms, int32_t n_kernels) {
+  if (!c || !kernel_ms || n_kernels < 1) return GPF_ERR_ARG;
+  if (n < 0) return fail(c, GPF_ERR_ARG, "negative step count");
+  int rc = c->ops->step(c, n, kernel_ms, n_kernels);
+  if (rc) return rc;
+  if (c->prm.health_every > 0) return check_health_result(c);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return GPF_OK;
+}
+
+int gpf_read(gpf_ctx* c, int32_t field, double* dst, size_t count) {
+  if (!c || !dst) return GPF_ERR_ARG;
+  const int comps = components(c, field);
+  if (comps < 0) return fail(c, GPF_ERR_ARG, "unknown field %d", field);
+  if (count != (size_t)comps * (size_t)c->cells)
+    return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, (size_t)comps * (size_t)c->cells);
+  double got = 0;
+  int rc = c->ops->read(c, field, &got);
+  if (rc) return rc;
+  HIP_OR_FAIL(c, hipMemcpyAsync(dst, c->scratch.ptr, count * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return GPF_OK;
+}
+
+int gpf_read_device(gpf_ctx* c, int32_t field, void* dst, size_t bytes) {
+  if (!c || !dst) return GPF_ERR_ARG;
+  const int comps = components(c, field);
+  if (field != GPF_PHI && field != GPF_MU && field != GPF_U && field != GPF_F)
+    return fail(c, GPF_ERR_ARG, "field %d has no native device copy", field);
+  if (bytes != (size_t)comps * (size_t)c->cells * c->esize)
+    return fail(c, GPF_ERR_ARG, "bytes %zu, expected %zu", bytes, (size_t)comps * (size_t)c->cells * c->esize);
+  return c->ops->read_native(c, field, dst);
+}
+
+int gpf_write(gpf_ctx* c, int32_t field, const double* src, size_t count) {
+  if (!c || !src) return GPF_ERR_ARG;
+  int rc = write_host(c, field, src, count);
+  if (rc) return rc;
+  // a written state starts a fresh health record
+  HIP_OR_FAIL(c, hipMemsetAsync(c->badstep.ptr, 0xff, sizeof(unsigned long long), c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return GPF_OK;
+}
+
+int gpf_reduce(gpf_ctx* c, int32_t which, double* out) {
+  if (!c || !out) return GPF_ERR_ARG;
+  if (which != GPF_SUM_SOLUTE && which != GPF_SUM_MASS) return fail(c, GPF_ERR_ARG, "unknown reduction %d", which);
+  return c->ops->reduce(c, which, out);
+}
+
+int gpf_set_param(gpf_ctx* c, const char* name, double value) {
+  if (!c || !name) return GPF_ERR_ARG;
+  gpf_params p = c->prm;
+  int rc = set_named(c, p, name, value);
+  if (rc) return rc;
+  rc = validate(c, &c->grid, c->N, c->nc + 1, &p);
+  if (rc) return rc;
+  c->prm = p;
+  return GPF_OK;
+}
+
+int64_t gpf_step_index(const gpf_ctx* c) { return c ? c->step : -1; }
+
+int gpf_set_step_index(gpf_ctx* c, int64_t n) {
+  if (!c) return GPF_ERR_ARG;
+  if (n < 0) return fail(c, GPF_ERR_ARG, "negative step index");
+  c->step = n;
+  return GPF_OK;
+}
+
+const char* gpf_last_error(const gpf_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+const char* gpf_status_string(int s) {
+  switch (s) {
+    case GPF_OK: return "ok";
+    case GPF_ERR_ARG: return "invalid argument";
+    case GPF_ERR_PARAM: return "invalid parameter";
+    case GPF_ERR_NOMEM: return "out of device memory";
+    case GPF_ERR_DEVICE: return "HIP error";
+    case GPF_ERR_NONFINITE: return "non-finite state";
+    case GPF_ERR_STATE: return "invalid state";
+    case GPF_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+void gpf_destroy(gpf_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,254 @@
+"""Python binding of libgpf.so (include/gpf.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of the library.  PyTorch
+supplies device memory (its caching allocator, through the library's
+allocation callbacks) and the stream the kernels run on.  There is no
+fallback: if libgpf.so is missing or no GPU is present, calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpf.so")
+
+GPF_OK = 0
+STATUS = {0: "GPF_OK", -1: "GPF_ERR_ARG", -2: "GPF_ERR_PARAM", -3: "GPF_ERR_NOMEM",
+          -4: "GPF_ERR_DEVICE", -5: "GPF_ERR_NONFINITE", -6: "GPF_ERR_STATE",
+          -7: "GPF_ERR_UNSUPPORTED"}
+FIELDS = {"phi": 0, "mu": 1, "f": 2, "rho": 3, "u": 4, "c": 5, "T": 6, "flags": 7, "fpost": 8}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+
+class GPFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridC(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double),
+                ("periodic_mask", ctypes.c_uint32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class ParamsC(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("precision", ctypes.c_int32), ("potential", ctypes.c_int32),
+        ("dt", ctypes.c_double), ("eps", ctypes.c_double), ("tau_pf", ctypes.c_double),
+        ("gamma", (ctypes.c_double * 3) * 3), ("delta", (ctypes.c_double * 3) * 3),
+        ("chi", (ctypes.c_double * 2) * 2), ("c0", (ctypes.c_double * 2) * 3),
+        ("dS", ctypes.c_double * 3), ("T_E", ctypes.c_double), ("T_iso", ctypes.c_double),
+        ("D", (ctypes.c_double * 2) * 3),
+        ("G", ctypes.c_double), ("V", ctypes.c_double), ("y0", ctypes.c_double),
+        ("pull_axis", ctypes.c_int32),
+        ("tau_lb", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("gbeta", ctypes.c_double * 2), ("c_ref", ctypes.c_double * 2),
+        ("grav_axis", ctypes.c_int32), ("grav_sign", ctypes.c_int32),
+        ("h_drag", ctypes.c_double), ("W0", ctypes.c_double), ("lid_u", ctypes.c_double),
+        ("init_kind", ctypes.c_int32), ("init_center", ctypes.c_double * 3),
+        ("init_radius", ctypes.c_double), ("lam_width", ctypes.c_double),
+        ("lam_height", ctypes.c_double), ("mu_inf", ctypes.c_double * 2),
+        ("noise_sigma", ctypes.c_double), ("health_every", ctypes.c_int64),
+        ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2608_26908_amd/build.py` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        L.gpf_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(GridC), i32, i32,
+                               ctypes.POINTER(ParamsC), ctypes.c_uint64]
+        L.gpf_set_stream.argtypes = [vp, vp]
+        L.gpf_step.argtypes = [vp, i64]
+        L.gpf_step_timed.argtypes = [vp, i64, dp, i32]
+        L.gpf_read.argtypes = [vp, i32, dp, ctypes.c_size_t]
+        L.gpf_read_device.argtypes = [vp, i32, vp, ctypes.c_size_t]
+        L.gpf_write.argtypes = [vp, i32, dp, ctypes.c_size_t]
+        L.gpf_reduce.argtypes = [vp, i32, dp]
+        L.gpf_set_param.argtypes = [vp, ctypes.c_char_p, ctypes.c_double]
+        L.gpf_set_step_index.argtypes = [vp, i64]
+        L.gpf_step_index.restype = i64
+        L.gpf_step_index.argtypes = [vp]
+        L.gpf_last_error.restype = ctypes.c_char_p
+        L.gpf_last_error.argtypes = [vp]
+        L.gpf_status_string.restype = ctypes.c_char_p
+        L.gpf_status_string.argtypes = [ctypes.c_int]
+        L.gpf_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _fill(dst, src):
+    a = np.asarray(src, dtype=float)
+    if a.ndim == 1:
+        for i, v in enumerate(a):
+            dst[i] = float(v)
+    else:
+        for i in range(a.shape[0]):
+            for j in range(a.shape[1]):
+                dst[i][j] = float(a[i, j])
+
+
+def make_grid(cfg):
+    g = GridC()
+    g.dim = cfg["dim"]
+    for a in range(3):
+        g.n[a] = int(cfg["n"][a]) if a < cfg["dim"] else 1
+    g.dx = float(cfg["dx"])
+    g.periodic_mask = sum(1 << a for a in range(cfg["dim"]) if cfg["periodic"][a])
+    return g
+
+
+def make_params(cfg, precision):
+    p = ParamsC()
+    p.lattice = 0 if cfg["dim"] == 2 else 1
+    p.precision = PRECISION[precision]
+    p.potential = {"obstacle": 0, "well": 1}[cfg.get("potential", "obstacle")]
+    for k in ("dt", "eps", "tau_pf", "T_E", "T_iso", "G", "V", "y0", "tau_lb", "rho0",
+              "h_drag", "W0", "lid_u", "init_radius", "lam_width", "lam_height", "noise_sigma"):
+        setattr(p, k, float(cfg.get(k, 0.0)))
+    p.pull_axis = int(cfg.get("pull_axis", 1))
+    p.grav_axis = int(cfg.get("grav_axis", 1))
+    p.grav_sign = int(cfg.get("grav_sign", -1))
+    p.init_kind = {"seed": 0, "lamellae": 1, "liquid": 2}[cfg.get("init", "seed")]
+    for name in ("gamma", "delta", "chi", "c0", "dS", "D", "gbeta", "c_ref", "mu_inf"):
+        _fill(getattr(p, name), cfg[name])
+    _fill(p.init_center, cfg.get("init_center", [0.0, 0.0, 0.0]))
+    p.health_every = int(cfg.get("health_every", 0))
+    return p
+
+
+class Sim:
+    """One simulation context of the HIP library.
+
+    cfg: a workload dict (paper_2608_26908_amd.workloads); precision 'fp64'
+    or 'fp32' (default: cfg['precision']).  Device memory comes from torch's
+    caching allocator unless torch_alloc=False (then hipMalloc); kernels run
+    on torch's current stream."""
+
+    def __init__(self, cfg, precision=None, seed=None, torch_alloc=True, health_every=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the library runs only on the device")
+        L = lib()
+        self.cfg = dict(cfg)
+        if health_every is not None:
+            self.cfg["health_every"] = health_every
+        self.precision = precision or cfg.get("precision", "fp64")
+        self.dim, self.N, self.nc = cfg["dim"], cfg["N"], cfg["nc"]
+        self.n = tuple(int(v) for v in cfg["n"][: self.dim])
+        self.Q = 9 if self.dim == 2 else 19
+        self.cells = int(np.prod(self.n))
+        self._grid = make_grid(self.cfg)
+        self._params = make_params(self.cfg, self.precision)
+        if torch_alloc:
+            torch.cuda.init()
+
+            def _alloc(nbytes, user):
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+            self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+            self._params.dev_alloc, self._params.dev_free = self._cb
+        h = ctypes.c_void_p()
+        s = cfg.get("seed", 1) if seed is None else seed
+        rc = L.gpf_init(ctypes.byref(h), ctypes.byref(self._grid), self.N, self.nc + 1,
+                        ctypes.byref(self._params), ctypes.c_uint64(s))
+        if rc != GPF_OK:
+            raise GPFError(rc, L.gpf_last_error(None).decode())
+        self._h = h
+        self._check(L.gpf_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, rc):
+        if rc != GPF_OK:
+            raise GPFError(rc, lib().gpf_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gpf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n))
+
+    def components(self, field):
+        return {"phi": self.N, "mu": self.nc, "f": self.Q, "rho": 1, "u": self.dim,
+                "c": self.nc, "T": 1, "flags": 1, "fpost": self.Q}[field]
+
+    # -- the C ABI ---------------------------------------------------------
+    @property
+    def step_index(self):
+        return lib().gpf_step_index(self._h)
+
+    @step_index.setter
+    def step_index(self, n):
+        self._check(lib().gpf_set_step_index(self._h, int(n)))
+
+    def checkpoint(self):
+        """exact copy of the state (bitwise resumable)"""
+        return {k: self.read(k) for k in ("phi", "mu", "u", "fpost")}, self.step_index
+
+    def restore(self, ckpt):
+        state, n = ckpt
+        for k, v in state.items():
+            self.write(k, v)
+        self.step_index = n
+
+    def step(self, n=1):
+        self._check(lib().gpf_step(self._h, int(n)))
+
+    def step_timed(self, n=1):
+        ms = (ctypes.c_double * 2)()
+        self._check(lib().gpf_step_timed(self._h, int(n), ms, 2))
+        return float(ms[0]), float(ms[1])
+
+    def read(self, field):
+        comps = self.components(field)
+        out = np.empty(comps * self.cells, dtype=np.float64)
+        self._check(lib().gpf_read(self._h, FIELDS[field],
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+        return out.reshape((comps,) + self.shape)
+
+    def read_device(self, field):
+        import torch
+        dt = torch.float64 if self.precision == "fp64" else torch.float32
+        t = torch.empty((self.components(field),) + self.shape, dtype=dt, device="cuda")
+        self._check(lib().gpf_read_device(self._h, FIELDS[field], ctypes.c_void_p(t.data_ptr()),
+                                          t.numel() * t.element_size()))
+        return t
+
+    def write(self, field, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float64).ravel()
+        self._check(lib().gpf_write(self._h, FIELDS[field],
+                                    a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size))
+
+    def reduce(self, which):
+        out = (ctypes.c_double * 2)()
+        self._check(lib().gpf_reduce(self._h, {"solute": 0, "mass": 1}[which], out))
+        return np.array(out[: self.nc]) if which == "solute" else float(out[0])
+
+    def set_param(self, name, value):
+        self._check(lib().gpf_set_param(self._h, name.encode(), float(value)))
