@@ -159,7 +159,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_mulbm (chemical potential + LBM collide/stream)",
+                     "kernel": "k_mulbm_z (chemical potential + LBM collide/stream, z-marching)",
                      "bytes_per_lup": b32,
                      "step_frac": round(b32 * cells / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_ms": {"k_phi": round(r32["k_phi_ms"], 4), "k_mulbm": round(r32["k_mulbm_ms"], 4)},

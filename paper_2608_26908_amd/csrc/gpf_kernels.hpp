@@ -1,10 +1,10 @@
 // gpf_kernels.hpp -- HIP kernels of the coupled GP phase-field / LBM step.
 //
-// One step = two launches on a 64 x 4 (x, y) block grid, z on blockIdx.z:
-//   k_phi    phi^n, mu^n            -> phi^{n+1}          (Eq. PhfGrand, Sec. 2.1)
-//   k_mulbm  phi^n, phi^{n+1}, mu^n, U^{n-1}, f*^{n-1}
-//                                   -> mu^{n+1}, U^n, f*^n (Eq. conc; Eqs. LBMEq_1,
-//                                      f^eq, discreteForce, buoyancy, rhovel)
+// One step = two z-marching launches over TX x TY tiles of (x, y):
+//   k_phi_z    phi^n, mu^n            -> phi^{n+1}          (Eq. PhfGrand, Sec. 2.1)
+//   k_mulbm_z  phi^n, phi^{n+1}, mu^n, U^{n-1}, f*^{n-1}
+//                                     -> mu^{n+1}, U^n, f*^n (Eq. conc; Eqs. LBMEq_1,
+//                                        f^eq, discreteForce, buoyancy, rhovel)
 // f buffers hold post-collision, pre-streaming populations as deviations
 // f - w_k rho0; streaming is a pull at the start of k_mulbm, with half-way
 // bounce-back where the source lies behind a wall.  All buffers are A-B:
@@ -14,8 +14,6 @@
 
 namespace gpf {
 
-constexpr int BX = 64;
-constexpr int BY = 4;
 
 // Population k of f^n at cell (x, y, z) = P, as a deviation from w_k rho0:
 // pulled from the stored post-collision f* of the upstream cell P - c_k, or,
@@ -48,27 +46,14 @@ __device__ __forceinline__ R pull_f(const KP<R>& p, const R* __restrict__ fin, i
 // ---------------------------------------------------------------------------
 // Phase field: active set, right-hand side, projection.
 // ---------------------------------------------------------------------------
+// phi^{n+1} of cell (x, y, z) from phi^n on its 9 (2D) / 19 (3D) point
+// neighbourhood v[phase][dz+1][dy+1][dx+1] (walls mirrored, periodic axes
+// wrapped; the corners of the 3x3x3 cube are not used) and mu^n at the cell.
 template <int D, int N, int NC, class R>
-__global__ void __launch_bounds__(BX * BY)
-k_phi(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
-      R tshift) {
-  const int x = blockIdx.x * BX + threadIdx.x;
-  const int y = blockIdx.y * BY + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= p.n[0] || y >= p.n[1]) return;
+__device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N][3][3][3],
+                                                 const R* __restrict__ mu, int x, int y, int z,
+                                                 R tshift, R (&res)[N]) {
   const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
-
-  // neighbour coordinates (wall: mirror, periodic: wrap)
-  int xs[3], ys[3], zs[3];
-#pragma unroll
-  for (int s = -1; s <= 1; ++s) {
-    xs[s + 1] = nb_field(x, s, p.n[0], p.per[0]);
-    ys[s + 1] = nb_field(y, s, p.n[1], p.per[1]);
-    zs[s + 1] = (D == 3) ? nb_field(z, s, p.n[2], p.per[2]) : 0;
-  }
-  // the 9 (2D) / 19 (3D) point neighbourhood: offsets with at most two
-  // non-zero components; corners of the 3x3x3 cube are never touched
-  R v[N][3][3][3];
   unsigned active = 0u;
 #pragma unroll
   for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
@@ -77,19 +62,14 @@ k_phi(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restric
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         if (dx != 0 && dy != 0 && dz != 0) continue;
-        const int64_t j = (int64_t)zs[dz + 1] * p.sz + (int64_t)ys[dy + 1] * p.sy + xs[dx + 1];
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-          R val = phi[b * p.cells + j];
-          v[b][dz + 1][dy + 1][dx + 1] = val;
-          if (val > R(0)) active |= 1u << b;
-        }
+        for (int b = 0; b < N; ++b)
+          if (v[b][dz + 1][dy + 1][dx + 1] > R(0)) active |= 1u << b;
       }
-
   const int na = __builtin_popcount(active);
   if (na <= 1) {  // bulk: phi unchanged
 #pragma unroll
-    for (int b = 0; b < N; ++b) phi_out[b * p.cells + P] = v[b][1][1][1];
+    for (int b = 0; b < N; ++b) res[b] = v[b][1][1][1];
     return;
   }
 
@@ -221,7 +201,6 @@ k_phi(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restric
   }
   R out[3];
   project_simplex<R>(cnt, vv, out);
-  R res[N];
 #pragma unroll
   for (int b = 0; b < N; ++b) res[b] = R(0);
 #pragma unroll
@@ -231,36 +210,38 @@ k_phi(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restric
       for (int b = 0; b < N; ++b)
         if (which[j] == b) res[b] = out[j];
     }
-#pragma unroll
-  for (int b = 0; b < N; ++b) phi_out[b * p.cells + P] = res[b];
 }
+
 
 // ---------------------------------------------------------------------------
 // Chemical potential + lattice Boltzmann (forces, moments, BGK + Guo, pull
 // streaming).
 // ---------------------------------------------------------------------------
+// mu^{n+1}, U^n and the post-collision populations of cell (x, y, z), given
+// the values it reads around itself:
+//   ph1n[0] / mun[0]: phi^{n+1} / mu^n at the cell, ph1n[1 + 2a + s] / mun[..]
+//   at its -e_a (s = 0) and +e_a (s = 1) neighbours (wrapped on periodic
+//   axes; never used across walls); uc: U^{n-1} at the cell; un[a][s]: the
+//   a-component of U^{n-1} at those neighbours; ph0: phi^n at the cell.
+// The populations are pulled from fin (the previous post-collision f*).
+// ---------------------------------------------------------------------------
 template <int D, int N, int NC, class R>
-__global__ void __launch_bounds__(BX * BY)
-k_mulbm(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
-        const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
-        R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout) {
+__device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
+                                           const R (&ph1n)[2 * D + 1][N],
+                                           const R (&mun)[2 * D + 1][NC], const R (&uc)[D],
+                                           const R (&un)[D][2], const R (&ph0)[N],
+                                           const R* __restrict__ fin, R* __restrict__ mu_out,
+                                           R* __restrict__ u_out, R* __restrict__ fout) {
   using L = Lat<D>;
-  const int x = blockIdx.x * BX + threadIdx.x;
-  const int y = blockIdx.y * BY + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= p.n[0] || y >= p.n[1]) return;
   const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
   const int pos[3] = {x, y, z};
-  const int64_t stride[3] = {1, p.sy, p.sz};
 
-  // per-cell quantities at phi^{n+1}: h, c* = sum h C(mu^n), M = sum phi D chi
-  auto quant = [&](int64_t j, R (&M)[NC][NC], R (&cs)[NC], R (&m)[NC]) {
+  // per-cell quantities at phi^{n+1}: c* = sum h C(mu^n), M = sum phi D chi
+  auto quant = [&](int slot, R (&M)[NC][NC], R (&cs)[NC]) {
     R ph[N], h[N];
 #pragma unroll
-    for (int b = 0; b < N; ++b) ph[b] = phi1[b * p.cells + j];
+    for (int b = 0; b < N; ++b) ph[b] = ph1n[slot][b];
     interp_h<N, R>(ph, h);
-#pragma unroll
-    for (int i = 0; i < NC; ++i) m[i] = mu[i * p.cells + j];
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
       cs[i] = R(0);
@@ -273,7 +254,7 @@ k_mulbm(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
       for (int i = 0; i < NC; ++i) {
         R C = p.c0[b][i];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) C += p.chi[i][k] * m[k];
+        for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mun[slot][k];
         cs[i] += h[b] * C;
 #pragma unroll
         for (int k = 0; k < NC; ++k) M[i][k] += ph[b] * p.D[b][i] * p.chi[i][k];
@@ -281,8 +262,8 @@ k_mulbm(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
     }
   };
 
-  R MP[NC][NC], cP[NC], mP[NC];
-  quant(P, MP, cP, mP);
+  R MP[NC][NC], cP[NC];
+  quant(0, MP, cP);
   R divJ[NC];
 #pragma unroll
   for (int i = 0; i < NC; ++i) divJ[i] = R(0);
@@ -290,33 +271,29 @@ k_mulbm(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
   const R idx = R(1) / p.dx;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const R uP = uold[a * p.cells + P];
 #pragma unroll
-    for (int s = -1; s <= 1; s += 2) {
+    for (int si = 0; si < 2; ++si) {
+      const int s = si ? 1 : -1;
       const bool wall = !p.per[a] && ((s < 0 && pos[a] == 0) || (s > 0 && pos[a] == p.n[a] - 1));
       if (wall) continue;
-      const int q = nb_field(pos[a], s, p.n[a], p.per[a]);
-      const int64_t Qj = P + (int64_t)(q - pos[a]) * stride[a];
-      R MQ[NC][NC], cQ[NC], mQ[NC];
-      quant(Qj, MQ, cQ, mQ);
-      const R uf = R(0.5) * (uP + uold[a * p.cells + Qj]) * conv;
+      const int slot = 1 + 2 * a + si;
+      R MQ[NC][NC], cQ[NC];
+      quant(slot, MQ, cQ);
+      const R uf = R(0.5) * (uc[a] + un[a][si]) * conv;
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
         R JD = R(0);
 #pragma unroll
         for (int k = 0; k < NC; ++k)
-          JD += -R(0.5) * (MP[i][k] + MQ[i][k]) * (R(s) * (mQ[k] - mP[k]) * idx);
+          JD += -R(0.5) * (MP[i][k] + MQ[i][k]) * (R(s) * (mun[slot][k] - mun[0][k]) * idx);
         const R JA = uf * R(0.5) * (cP[i] + cQ[i]);
         divJ[i] += R(s) * (JD + JA) * idx;
       }
     }
   }
-  R ph0[N], ph1[N], h0[N], h1[N];
+  R ph1[N], h0[N], h1[N];
 #pragma unroll
-  for (int b = 0; b < N; ++b) {
-    ph0[b] = phi0[b * p.cells + P];
-    ph1[b] = phi1[b * p.cells + P];
-  }
+  for (int b = 0; b < N; ++b) ph1[b] = ph1n[0][b];
   interp_h<N, R>(ph0, h0);
   interp_h<N, R>(ph1, h1);
   R Dl[NC];
@@ -330,19 +307,19 @@ k_mulbm(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
     for (int i = 0; i < NC; ++i) {
       R C = p.c0[b][i];
 #pragma unroll
-      for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mP[k];
+      for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mun[0][k];
       Dl[i] -= C * (h1[b] - h0[b]);
     }
   }
   R mn[NC];
   if (NC == 1) {
-    mn[0] = mP[0] + Dl[0] / (sh * p.chi[0][0]);
+    mn[0] = mun[0][0] + Dl[0] / (sh * p.chi[0][0]);
   } else {
     const R a11 = sh * p.chi[0][0], a12 = sh * p.chi[0][1];
     const R a21 = sh * p.chi[1][0], a22 = sh * p.chi[1][NC - 1];
     const R det = a11 * a22 - a12 * a21;
-    mn[0] = mP[0] + (a22 * Dl[0] - a12 * Dl[NC - 1]) / det;
-    mn[NC - 1] = mP[NC - 1] + (-a21 * Dl[0] + a11 * Dl[NC - 1]) / det;
+    mn[0] = mun[0][0] + (a22 * Dl[0] - a12 * Dl[NC - 1]) / det;
+    mn[NC - 1] = mun[0][NC - 1] + (-a21 * Dl[0] + a11 * Dl[NC - 1]) / det;
   }
 #pragma unroll
   for (int i = 0; i < NC; ++i) mu_out[i * p.cells + P] = mn[i];
@@ -384,20 +361,22 @@ k_mulbm(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
                           : R(0);
     F[a] = FB[a] - p.kappa * rho * sol * u[a];
   }
-  R uu = R(0);
+  R uu = R(0), uF = R(0);
 #pragma unroll
-  for (int a = 0; a < D; ++a) uu += u[a] * u[a];
+  for (int a = 0; a < D; ++a) {
+    uu += u[a] * u[a];
+    uF += u[a] * F[a];
+  }
   const R pref = R(1) - R(0.5) / p.tau_lb;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    R cu = R(0), cF = R(0), uF = R(0);
+    R cu = R(0), cF = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       if (L::c(k, a) != 0) {
         cu += R(L::c(k, a)) * u[a];
         cF += R(L::c(k, a)) * F[a];
       }
-      uF += u[a] * F[a];
     }
     const R feq = p.w[k] * (dr + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
     const R S = pref * p.w[k] * (R(3) * (cF - uF) + R(9) * cu * cF);
@@ -405,6 +384,214 @@ k_mulbm(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) u_out[a * p.cells + P] = u[a];
+}
+
+// coordinate along one axis of a tile-halo cell: periodic axes wrap, walls
+// clamp (values across a wall are never used: wall faces carry no flux)
+__device__ __forceinline__ int wrap_or_clamp(int v, int n, int per) {
+  if (per) return ((v % n) + n) % n;
+  return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+// Tile of a z-marching block.  Work-groups are dealt to the 8 XCDs
+// round-robin; renumbering gives each XCD a contiguous range of tiles, so
+// tiles that are neighbours in y and z share its L2.
+struct Tile {
+  int x0, y0, z0, z1;
+};
+__device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty, int zc, int nz,
+                                        int D) {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned per8 = nb / 8u;
+  const unsigned lb = (b < per8 * 8u) ? (b % 8u) * per8 + b / 8u : b;
+  Tile t;
+  t.x0 = (int)(lb % (unsigned)tiles_x) * tx;
+  t.y0 = (int)((lb / (unsigned)tiles_x) % (unsigned)tiles_y) * ty;
+  const int tz = (int)(lb / ((unsigned)tiles_x * (unsigned)tiles_y));
+  t.z0 = (D == 3) ? tz * zc : 0;
+  t.z1 = (D == 3) ? min(t.z0 + zc, nz) : 1;
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Phase field, z-marching: a block owns a TX x TY tile and walks along z
+// through planes [z0, z1).  phi^n of the tile plus a one-cell halo is kept in
+// a three-plane LDS ring (planes z-1, z, z+1), so every phi^n value is read
+// from memory once per block and the 9/19-point stencil reads LDS.
+// ---------------------------------------------------------------------------
+template <int D, int N, int NC, class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
+        R tshift, int tiles_x, int tiles_y, int zc) {
+  constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
+  __shared__ R ring[3][N][HC];
+  const Tile T = tile_of(tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = T.x0 + lx, y = T.y0 + ly;
+  const bool own = x < p.n[0] && y < p.n[1];
+  const int c0 = (ly + 1) * HX + (lx + 1);
+
+  auto load = [&](int zz, int slot) {
+    const int zg = (D == 3) ? wrap_or_clamp(zz, p.n[2], p.per[2]) : 0;
+    for (int i = tid; i < HC; i += TX * TY) {
+      const int gx = wrap_or_clamp(T.x0 - 1 + i % HX, p.n[0], p.per[0]);
+      const int gy = wrap_or_clamp(T.y0 - 1 + i / HX, p.n[1], p.per[1]);
+      const int64_t j = (int64_t)zg * p.sz + (int64_t)gy * p.sy + gx;
+#pragma unroll
+      for (int q = 0; q < N; ++q) ring[slot][q][i] = phi[q * p.cells + j];
+    }
+  };
+  auto update = [&](int z, int sm, int s0, int sp) {
+    if (!own) return;
+    R v[N][3][3][3];
+    const int sl[3] = {sm, s0, sp};
+#pragma unroll
+    for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (dx != 0 && dy != 0 && dz != 0) continue;
+#pragma unroll
+          for (int q = 0; q < N; ++q) v[q][dz + 1][dy + 1][dx + 1] = ring[sl[dz + 1]][q][c0 + dy * HX + dx];
+        }
+    R res[N];
+    phi_from_stencil<D, N, NC, R>(p, v, mu, x, y, z, tshift, res);
+    const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
+#pragma unroll
+    for (int q = 0; q < N; ++q) phi_out[q * p.cells + P] = res[q];
+  };
+
+  if (D == 2) {
+    load(0, 1);
+    __syncthreads();
+    update(0, 1, 1, 1);
+    return;
+  }
+  // ring slot of plane zz: (zz - z0 + 1) mod 3
+  load(T.z0 - 1, 0);
+  load(T.z0, 1);
+  for (int z = T.z0; z < T.z1; ++z) {
+    const int k = z - T.z0;
+    load(z + 1, (k + 2) % 3);
+    __syncthreads();
+    update(z, k % 3, (k + 1) % 3, (k + 2) % 3);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chemical potential + LBM, z-marching.  Each thread walks its (x, y) column
+// along z: phi^{n+1}, mu^n and U_z^{n-1} of the planes z-1, z, z+1 at its own
+// column stay in registers (one new plane is loaded per step), and the
+// in-plane neighbours (x +- 1, y +- 1) of phi^{n+1}, mu^n, U_x, U_y come from
+// an LDS tile with a one-cell halo.
+// ---------------------------------------------------------------------------
+template <int D, int N, int NC, class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
+          const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
+          R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout, int tiles_x,
+          int tiles_y, int zc) {
+  constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
+  constexpr int NV = N + NC + 2;  // phi^{n+1}, mu^n, U_x, U_y per halo cell
+  __shared__ R sh[NV][HC];
+  const Tile T = tile_of(tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = T.x0 + lx, y = T.y0 + ly;
+  const bool own = x < p.n[0] && y < p.n[1];
+  const int c0 = (ly + 1) * HX + (lx + 1);
+  const int xo = own ? x : 0, yo = own ? y : 0;
+  const int64_t col = (int64_t)yo * p.sy + xo;
+
+  // own column, planes z-1 (index 0), z (1), z+1 (2)
+  R cph[3][N], cmu[3][NC], cuz[3];
+  auto load_col = [&](int zz, int i) {
+    const int zg = (D == 3) ? wrap_or_clamp(zz, p.n[2], p.per[2]) : 0;
+    const int64_t j = (int64_t)zg * p.sz + col;
+#pragma unroll
+    for (int q = 0; q < N; ++q) cph[i][q] = phi1[q * p.cells + j];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) cmu[i][q] = mu[q * p.cells + j];
+    cuz[i] = (D == 3) ? uold[(D - 1) * p.cells + j] : R(0);
+  };
+  if (D == 3) {
+    load_col(T.z0 - 1, 0);
+    load_col(T.z0, 1);
+  } else {
+    load_col(0, 1);
+  }
+  for (int z = T.z0; z < T.z1; ++z) {
+    if (D == 3) load_col(z + 1, 2);
+    // in-plane tile + halo of plane z
+    for (int i = tid; i < HC; i += TX * TY) {
+      const int gx = wrap_or_clamp(T.x0 - 1 + i % HX, p.n[0], p.per[0]);
+      const int gy = wrap_or_clamp(T.y0 - 1 + i / HX, p.n[1], p.per[1]);
+      const int64_t j = (int64_t)z * p.sz + (int64_t)gy * p.sy + gx;
+#pragma unroll
+      for (int q = 0; q < N; ++q) sh[q][i] = phi1[q * p.cells + j];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) sh[N + q][i] = mu[q * p.cells + j];
+      sh[N + NC][i] = uold[j];
+      sh[N + NC + 1][i] = uold[p.cells + j];
+    }
+    __syncthreads();
+    if (own) {
+      const int64_t P = (int64_t)z * p.sz + col;
+      R ph1n[2 * D + 1][N], mun[2 * D + 1][NC], uc[D], un[D][2], ph0[N];
+      const int off[4] = {-1, 1, -HX, HX};
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        ph1n[0][q] = cph[1][q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ph1n[1 + j][q] = sh[q][c0 + off[j]];
+        if (D == 3) {
+          ph1n[2 * D - 1][q] = cph[0][q];
+          ph1n[2 * D][q] = cph[2][q];
+        }
+        ph0[q] = phi0[q * p.cells + P];
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        mun[0][q] = cmu[1][q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mun[1 + j][q] = sh[N + q][c0 + off[j]];
+        if (D == 3) {
+          mun[2 * D - 1][q] = cmu[0][q];
+          mun[2 * D][q] = cmu[2][q];
+        }
+      }
+      uc[0] = sh[N + NC][c0];
+      uc[1] = sh[N + NC + 1][c0];
+      un[0][0] = sh[N + NC][c0 - 1];
+      un[0][1] = sh[N + NC][c0 + 1];
+      un[1][0] = sh[N + NC + 1][c0 - HX];
+      un[1][1] = sh[N + NC + 1][c0 + HX];
+      if (D == 3) {
+        uc[D - 1] = cuz[1];
+        un[D - 1][0] = cuz[0];
+        un[D - 1][1] = cuz[2];
+      }
+      mulbm_core<D, N, NC, R>(p, x, y, z, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout);
+    }
+    __syncthreads();
+    if (D == 3) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        cph[0][q] = cph[1][q];
+        cph[1][q] = cph[2][q];
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        cmu[0][q] = cmu[1][q];
+        cmu[1][q] = cmu[2][q];
+      }
+      cuz[0] = cuz[1];
+      cuz[1] = cuz[2];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

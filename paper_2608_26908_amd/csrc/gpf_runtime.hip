@@ -171,10 +171,6 @@ struct Ops {
   int (*read_native)(gpf_ctx*, int, void*);
 };
 
-inline dim3 step_grid(const gpf_ctx* c) {
-  return dim3((unsigned)((c->n[0] + gpf::BX - 1) / gpf::BX), (unsigned)((c->n[1] + gpf::BY - 1) / gpf::BY),
-              (unsigned)c->n[2]);
-}
 inline unsigned lin_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int D, int N, int NC, class R>
@@ -192,9 +188,26 @@ struct Impl {
     return GPF_OK;
   }
 
+  template <int TY>
+  static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, int s, int t, R ts, int zc, hipEvent_t* ev) {
+    constexpr int TX = 64;
+    const int tiles_x = (int)((c->n[0] + TX - 1) / TX), tiles_y = (int)((c->n[1] + TY - 1) / TY);
+    const int tiles_z = (D == 3) ? (int)((c->n[2] + zc - 1) / zc) : 1;
+    const dim3 grid((unsigned)tiles_x * (unsigned)tiles_y * (unsigned)tiles_z), block(TX * TY);
+    if (ev) (void)hipEventRecord(ev[0], c->stream);
+    hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, P(c->phi[s]),
+                       P(c->mu[s]), P(c->phi[t]), ts, tiles_x, tiles_y, zc);
+    if (ev) (void)hipEventRecord(ev[1], c->stream);
+    hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, P(c->phi[s]),
+                       P(c->phi[t]), P(c->mu[s]), P(c->u[s]), P(c->f[s]), P(c->mu[t]), P(c->u[t]),
+                       P(c->f[t]), tiles_x, tiles_y, zc);
+    if (ev) (void)hipEventRecord(ev[2], c->stream);
+  }
+
   static int step(gpf_ctx* c, int64_t nsteps, double* kernel_ms, int nk) {
     gpf::KP<R> k = make_kp<R>(c);
-    const dim3 grid = step_grid(c), block(gpf::BX, gpf::BY, 1);
+    // tile 64 x 4, 8 planes per block (measured best of 64 x {4, 8} x {8..64} on 256^3)
+    constexpr int kZChunk = 8;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (kernel_ms) {
       for (int i = 0; i < 3; ++i) HIP_OR_FAIL(c, hipEventCreate(&ev[i]));
@@ -204,15 +217,9 @@ struct Impl {
     for (int64_t it = 0; it < nsteps; ++it) {
       const int s = c->cur, t = 1 - c->cur;
       const R ts = (R)tshift(c, c->step);
-      if (kernel_ms) HIP_OR_FAIL(c, hipEventRecord(ev[0], c->stream));
-      hipLaunchKernelGGL((gpf::k_phi<D, N, NC, R>), grid, block, 0, c->stream, k, P(c->phi[s]),
-                         P(c->mu[s]), P(c->phi[t]), ts);
-      if (kernel_ms) HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
-      hipLaunchKernelGGL((gpf::k_mulbm<D, N, NC, R>), grid, block, 0, c->stream, k, P(c->phi[s]),
-                         P(c->phi[t]), P(c->mu[s]), P(c->u[s]), P(c->f[s]), P(c->mu[t]),
-                         P(c->u[t]), P(c->f[t]));
+      launch_step<4>(c, k, s, t, ts, kZChunk, kernel_ms ? ev : nullptr);
+      HIP_OR_FAIL(c, hipGetLastError());
       if (kernel_ms) {
-        HIP_OR_FAIL(c, hipEventRecord(ev[2], c->stream));
         HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
         float a = 0.f, b = 0.f;
         HIP_OR_FAIL(c, hipEventElapsedTime(&a, ev[0], ev[1]));
@@ -220,7 +227,6 @@ struct Impl {
         if (nk > 0) kernel_ms[0] += a;
         if (nk > 1) kernel_ms[1] += b;
       }
-      HIP_OR_FAIL(c, hipGetLastError());
       c->cur = t;
       c->step += 1;
       if (H > 0 && (c->step % H == 0 || it == nsteps - 1)) {
