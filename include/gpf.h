@@ -174,6 +174,35 @@ int gpf_reduce(gpf_ctx* ctx, int32_t which, double* out);
  * "gbeta" / "gbeta1".  Re-validated like gpf_init. */
 int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
 
+/* Adjoint (reverse mode of the discrete step, hand-written kernels).
+ *
+ * gpf_record: the current state becomes checkpoint 0 of a recording; every
+ * later gpf_step stores a full-state checkpoint each `checkpoint_every`
+ * steps (device memory: (N + nc + dim + Q) * cells values per checkpoint).
+ * Errors: GPF_ERR_ARG (checkpoint_every < 1), GPF_ERR_NOMEM.
+ *
+ * gpf_adjoint: given dL/dphi at the current state (FP64 host array of
+ * N * cells values, layout of GPF_PHI), propagates the adjoint back through
+ * every step since gpf_record -- each segment between checkpoints is
+ * recomputed into a tape of checkpoint_every states -- and writes the FP64
+ * derivatives dL/dp for the named scalar parameters ("delta": the anisotropy
+ * strength of every pair that has one; "tau_pf": the relaxation of Eq.
+ * (PhfGrand); "D" / "D1": liquid diffusivity of solute 0 / 1; "gbeta" /
+ * "gbeta1": buoyancy products of Eq. (buoyancy)) to grads_out[0..n_names).
+ * The forward state is left unchanged.  Parameter derivatives are
+ * accumulated in FP64 in a fixed order; the adjoint fields have the
+ * context's precision.  Synchronises.  Errors: GPF_ERR_STATE (nothing
+ * recorded), GPF_ERR_ARG (count, unknown name, more than 6 names),
+ * GPF_ERR_NOMEM.
+ *
+ * gpf_adjoint_state: after gpf_adjoint, dL/d(initial recorded state) for
+ * GPF_PHI, GPF_MU, GPF_U (velocity of the step before) or GPF_F (the
+ * populations after streaming), FP64, components * cells values. */
+int gpf_record(gpf_ctx* ctx, int64_t checkpoint_every);
+int gpf_adjoint(gpf_ctx* ctx, const double* dL_dphi, size_t count, const char* const* names,
+                int32_t n_names, double* grads_out);
+int gpf_adjoint_state(gpf_ctx* ctx, int32_t field, double* host_dst, size_t count);
+
 /* Step counter n (it sets the time of the pulled temperature field).  The
  * setter is for resuming a checkpoint; n >= 0. */
 int64_t gpf_step_index(const gpf_ctx* ctx);

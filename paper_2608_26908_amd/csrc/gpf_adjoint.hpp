@@ -1,0 +1,928 @@
+// gpf_adjoint.hpp -- discrete adjoint of one coupled step (reverse mode of
+// the forward kernels, written by hand) and the FP64 parameter gradients.
+//
+// State at step n: X^n = (phi^n, mu^n, U^{n-1}, f^n), f^n the populations
+// after streaming (held on the device as the previous post-collision f*,
+// pulled on use).  One reverse step maps the adjoint of X^{n+1} to the adjoint
+// of X^n, reading X^n and X^{n+1} from the recomputed tape:
+//   k_adj_lbm   streaming transpose + collision VJP        -> lam f^n, lam phi_l', lam mu' (partial), d gbeta
+//   k_adj_w     w = chi_tot^{-1} lam mu'                   -> w, lam mu^n (direct term)
+//   k_adj_mu    faces of the mu update (gather)            -> lam mu^n, lam U^{n-1}, lam phi' (partial), lam phi^n (h^n), d D
+//   k_adj_phi1  projection + local phase-field terms        -> Rbar, lam phi^n, lam mu^n, d tau
+//   k_adj_phi2  face fluxes and cell terms (gather)         -> lam phi^n, d delta
+// Every kernel gathers into the cells it owns: no atomics, deterministic.
+// Parameter derivatives are reduced per block in FP64 and summed in a fixed
+// order.  Hessian-vector products of the gradient energy come from forward
+// mode through dAdq.
+#pragma once
+#include "gpf_kernels.hpp"
+
+namespace gpf {
+
+enum { G_DELTA = 0, G_TAU = 1, G_D0 = 2, G_D1 = 3, G_GB0 = 4, G_GB1 = 5, NG = 6 };
+constexpr int ADJ_BLOCK = 256;
+
+__device__ __forceinline__ void cell_coords(const int64_t P, const int64_t sy, const int64_t sz,
+                                            const int nx, const int ny, int& x, int& y, int& z) {
+  x = (int)(P % nx);
+  y = (int)((P / sy) % ny);
+  z = (int)(P / sz);
+}
+
+// per-block FP64 partial sums of the NG parameter derivatives, fixed order
+__device__ __forceinline__ void block_partials(double (&g)[NG], double* __restrict__ part) {
+  __shared__ double sh[NG][ADJ_BLOCK];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) sh[i][t] = g[i];
+  __syncthreads();
+  for (int s = ADJ_BLOCK / 2; s > 0; s >>= 1) {
+    if (t < s)
+#pragma unroll
+      for (int i = 0; i < NG; ++i) sh[i][t] += sh[i][t + s];
+    __syncthreads();
+  }
+  if (t == 0)
+#pragma unroll
+    for (int i = 0; i < NG; ++i) part[(int64_t)blockIdx.x * NG + i] = sh[i][0];
+}
+
+// phi^n neighbourhood of a cell, walls mirrored, periodic axes wrapped
+template <int D, int N, class R>
+__device__ __forceinline__ void load_stencil(const KP<R>& p, const R* __restrict__ phi, int x, int y,
+                                             int z, R (&v)[N][3][3][3]) {
+#pragma unroll
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (dx != 0 && dy != 0 && dz != 0) continue;
+        const int xx = nb_field(x, dx, p.n[0], p.per[0]);
+        const int yy = nb_field(y, dy, p.n[1], p.per[1]);
+        const int zz = (D == 3) ? nb_field(z, dz, p.n[2], p.per[2]) : 0;
+        const int64_t j = (int64_t)zz * p.sz + (int64_t)yy * p.sy + xx;
+#pragma unroll
+        for (int b = 0; b < N; ++b) v[b][dz + 1][dy + 1][dx + 1] = phi[b * p.cells + j];
+      }
+}
+
+// d^2 h_b / dphi_a dphi_g
+template <int N, class R>
+__device__ __forceinline__ R d2h(const R (&ph)[N], int b, int a, int g) {
+  R r = (a == b && g == b) ? R(6) - R(12) * ph[b] : R(0);
+  if (N == 3 && a != g) r += R(2) * ph[3 - a - g];
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// 1. streaming transpose + collision VJP
+// ---------------------------------------------------------------------------
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ phi1, const R* __restrict__ mu1,
+          const R* __restrict__ lf1, const R* __restrict__ lu1, R* __restrict__ lf0,
+          R* __restrict__ t_phil, R* __restrict__ t_mu, double* __restrict__ part) {
+  using L = Lat<D>;
+  const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
+  double gpart[NG] = {0, 0, 0, 0, 0, 0};
+  if (P < p.cells) {
+    int x, y, z;
+    cell_coords(P, p.sy, p.sz, p.n[0], p.n[1], x, y, z);
+    R f[L::Q], ob[L::Q];
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      f[k] = pull_f<D, R>(p, fst, x, y, z, P, k);
+      // f*_k(P) streams to f_k(P + c_k), or is reflected into f_{opp k}(P)
+      int dst[3] = {x + L::c(k, 0), y + L::c(k, 1), z + L::c(k, 2)};
+      bool in = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        if (L::c(k, a) == 0) continue;
+        if (dst[a] < 0 || dst[a] >= p.n[a]) {
+          if (p.per[a])
+            dst[a] = (dst[a] + p.n[a]) % p.n[a];
+          else
+            in = false;
+        }
+      }
+      ob[k] = in ? lf1[k * p.cells + (int64_t)dst[2] * p.sz + (int64_t)dst[1] * p.sy + dst[0]]
+                 : lf1[L::opp(k) * p.cells + P];
+    }
+    const R phil = phi1[(N - 1) * p.cells + P];
+    R mu[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) mu[i] = mu1[i * p.cells + P];
+    // ---- forward recomputation ----
+    R dr = R(0), mom[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) mom[a] = R(0);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      dr += f[k];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        if (L::c(k, a) != 0) mom[a] += R(L::c(k, a)) * f[k];
+    }
+    const R rho = p.rho0 + dr;
+    R Cl[NC], bsum = R(0);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      Cl[i] = p.c0[N - 1][i];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) Cl[i] += p.chi[i][k] * mu[k];
+      bsum += p.gbeta[i] * (Cl[i] - p.c_ref[i]);
+    }
+    const int ga = p.grav_axis;
+    R FB[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) FB[a] = R(0);
+    FB[ga] = -rho * phil * bsum * p.grav_sign;
+    const R sol = (R(1) - phil) * (R(1) - phil);
+    const R den = rho * (R(1) + R(0.5) * p.kappa * sol);
+    const bool moving = phil != R(0);
+    R u[D], F[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      u[a] = moving ? (mom[a] + R(0.5) * FB[a]) / den : R(0);
+      F[a] = FB[a] - p.kappa * rho * sol * u[a];
+    }
+    R uu = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) uu += u[a] * u[a];
+    const R pref = R(1) - R(0.5) / p.tau_lb;
+    // ---- reverse ----
+    R fb[L::Q], drb = R(0), rhob = R(0), uub = R(0), uFb = R(0), ub[D], Fb[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      ub[a] = lu1[a * p.cells + P];
+      Fb[a] = R(0);
+    }
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      R cu = R(0), cF = R(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        if (L::c(k, a) != 0) {
+          cu += R(L::c(k, a)) * u[a];
+          cF += R(L::c(k, a)) * F[a];
+        }
+      fb[k] = (R(1) - R(1) / p.tau_lb) * ob[k];
+      const R feqb = ob[k] / p.tau_lb, Sb = ob[k];
+      drb += p.w[k] * feqb;
+      rhob += p.w[k] * feqb * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+      const R cub = p.w[k] * feqb * rho * (R(3) + R(9) * cu) + R(9) * pref * p.w[k] * Sb * cF;
+      uub += -R(1.5) * p.w[k] * feqb * rho;
+      const R cFb = pref * p.w[k] * Sb * (R(3) + R(9) * cu);
+      uFb += -R(3) * pref * p.w[k] * Sb;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        if (L::c(k, a) != 0) {
+          ub[a] += cub * R(L::c(k, a));
+          Fb[a] += cFb * R(L::c(k, a));
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      ub[a] += R(2) * u[a] * uub + F[a] * uFb;
+      Fb[a] += u[a] * uFb;
+    }
+    // F = FB - kappa rho sol u
+    R FBb[D], solb = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      FBb[a] = Fb[a];
+      rhob += -p.kappa * sol * u[a] * Fb[a];
+      solb += -p.kappa * rho * u[a] * Fb[a];
+      ub[a] += -p.kappa * rho * sol * Fb[a];
+    }
+    // u = (m + FB / 2) / den where phi_l != 0
+    R mb[D], denb = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      mb[a] = moving ? ub[a] / den : R(0);
+      if (moving) {
+        FBb[a] += R(0.5) * ub[a] / den;
+        denb += -ub[a] * u[a] / den;
+      }
+    }
+    rhob += denb * (R(1) + R(0.5) * p.kappa * sol);
+    solb += denb * rho * R(0.5) * p.kappa;
+    R philb = -R(2) * (R(1) - phil) * solb;
+    rhob += -phil * bsum * p.grav_sign * FBb[ga];
+    philb += -rho * bsum * p.grav_sign * FBb[ga];
+    const R bb = -rho * phil * p.grav_sign * FBb[ga];
+    R mub[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) mub[k] = R(0);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      gpart[G_GB0 + i] = (double)((Cl[i] - p.c_ref[i]) * bb);
+      const R Clb = p.gbeta[i] * bb;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) mub[k] += p.chi[i][k] * Clb;
+    }
+    drb += rhob;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      R v = fb[k] + drb;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        if (L::c(k, a) != 0) v += mb[a] * R(L::c(k, a));
+      lf0[k * p.cells + P] = v;
+    }
+    t_phil[P] = philb;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) t_mu[i * p.cells + P] = mub[i];
+  }
+  block_partials(gpart, part);
+}
+
+// ---------------------------------------------------------------------------
+// 2. w = chi_tot^{-T} lam mu'   (chi_tot = sum_a h_a(phi^{n+1}) chi, symmetric)
+// ---------------------------------------------------------------------------
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_adj_w(KP<R> p, const R* __restrict__ phi1, const R* __restrict__ lmu1, const R* __restrict__ t_mu,
+        R* __restrict__ w, R* __restrict__ lmu0) {
+  const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
+  if (P >= p.cells) return;
+  R ph[N], h[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) ph[b] = phi1[b * p.cells + P];
+  interp_h<N, R>(ph, h);
+  R sh = R(0);
+#pragma unroll
+  for (int b = 0; b < N; ++b) sh += h[b];
+  R mb[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    mb[i] = lmu1[i * p.cells + P] + t_mu[i * p.cells + P];
+    lmu0[i * p.cells + P] = mb[i];
+  }
+  if (NC == 1) {
+    w[P] = mb[0] / (sh * p.chi[0][0]);
+  } else {
+    const R a11 = sh * p.chi[0][0], a12 = sh * p.chi[0][1];
+    const R a21 = sh * p.chi[1][0], a22 = sh * p.chi[1][NC - 1];
+    const R det = a11 * a22 - a12 * a21;
+    // transpose of the inverse
+    w[P] = (a22 * mb[0] - a21 * mb[NC - 1]) / det;
+    w[p.cells + P] = (-a12 * mb[0] + a11 * mb[NC - 1]) / det;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. the mu update, gathered over the faces of each cell
+// ---------------------------------------------------------------------------
+template <int N, int NC, class R>
+__device__ __forceinline__ void mu_quant(const KP<R>& p, const R (&ph)[N], const R (&m)[NC],
+                                         R (&M)[NC][NC], R (&cs)[NC]) {
+  R h[N];
+  interp_h<N, R>(ph, h);
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    cs[i] = R(0);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) M[i][k] = R(0);
+  }
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      R C = p.c0[b][i];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) C += p.chi[i][k] * m[k];
+      cs[i] += h[b] * C;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) M[i][k] += ph[b] * p.D[b][i] * p.chi[i][k];
+    }
+}
+
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_adj_mu(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1, const R* __restrict__ mu0,
+         const R* __restrict__ mu1, const R* __restrict__ u0, const R* __restrict__ w,
+         R* __restrict__ lmu0, R* __restrict__ lu0, R* __restrict__ t_phi1, R* __restrict__ lphi0,
+         double* __restrict__ part) {
+  const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
+  double gpart[NG] = {0, 0, 0, 0, 0, 0};
+  if (P < p.cells) {
+    int x, y, z;
+    cell_coords(P, p.sy, p.sz, p.n[0], p.n[1], x, y, z);
+    const int pos[3] = {x, y, z};
+    const int64_t stride[3] = {1, p.sy, p.sz};
+    R php[N], mp[NC], wp[NC], MP[NC][NC], cP[NC];
+#pragma unroll
+    for (int b = 0; b < N; ++b) php[b] = phi1[b * p.cells + P];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      mp[i] = mu0[i * p.cells + P];
+      wp[i] = w[i * p.cells + P];
+    }
+    mu_quant<N, NC, R>(p, php, mp, MP, cP);
+    R mub[NC], Mb[NC][NC], cb[NC], Ub[D];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      mub[i] = R(0);
+      cb[i] = R(0);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) Mb[i][k] = R(0);
+    }
+    const R conv = p.dx / p.dt, idx = R(1) / p.dx, dtdx = p.dt / p.dx;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      Ub[a] = R(0);
+      const R uaP = u0[a * p.cells + P];
+#pragma unroll
+      for (int si = 0; si < 2; ++si) {
+        const int s = si ? 1 : -1;
+        const bool wall = !p.per[a] && ((s < 0 && pos[a] == 0) || (s > 0 && pos[a] == p.n[a] - 1));
+        if (wall) continue;
+        const int q = nb_field(pos[a], s, p.n[a], p.per[a]);
+        const int64_t Qj = P + (int64_t)(q - pos[a]) * stride[a];
+        R phq[N], mq[NC], wq[NC], MQ[NC][NC], cQ[NC];
+#pragma unroll
+        for (int b = 0; b < N; ++b) phq[b] = phi1[b * p.cells + Qj];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          mq[i] = mu0[i * p.cells + Qj];
+          wq[i] = w[i * p.cells + Qj];
+        }
+        mu_quant<N, NC, R>(p, phq, mq, MQ, cQ);
+        const R uaQ = u0[a * p.cells + Qj];
+        // the face with left cell L and right cell R = L + e_a
+        const R sgn = (s > 0) ? R(1) : R(-1);  // +1: this cell is L
+        R Jb[NC], dmu[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          Jb[i] = dtdx * sgn * (wq[i] - wp[i]);
+          dmu[i] = sgn * (mq[i] - mp[i]);  // mu_R - mu_L
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+          for (int i = 0; i < NC; ++i) {
+            mub[k] += sgn * Jb[i] * R(0.5) * (MP[i][k] + MQ[i][k]) * idx;
+            Mb[i][k] += Jb[i] * (-R(0.5) * dmu[k] * idx);
+          }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          Ub[a] += Jb[i] * R(0.5) * conv * R(0.5) * (cP[i] + cQ[i]);
+          cb[i] += Jb[i] * R(0.5) * (uaP + uaQ) * conv * R(0.5);
+        }
+      }
+    }
+    // source term and chi_tot at the cell
+    R ph0[N], h0[N], h1[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) ph0[b] = phi0[b * p.cells + P];
+    interp_h<N, R>(ph0, h0);
+    interp_h<N, R>(php, h1);
+    R chidm[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      chidm[i] = R(0);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) chidm[i] += p.chi[i][k] * (mu1[k * p.cells + P] - mp[k]);
+    }
+    R wchidm = R(0);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) wchidm += wp[i] * chidm[i];
+    R h1b[N], h0b[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      R wC = R(0), cC = R(0);
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        R C = p.c0[b][i];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mp[k];
+        wC += wp[i] * C;
+        cC += cb[i] * C;
+      }
+      h1b[b] = -wC - wchidm + cC;
+      h0b[b] = wC;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        R wchi = R(0), cchi = R(0);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          wchi += wp[i] * p.chi[i][j];
+          cchi += cb[i] * p.chi[i][j];
+        }
+        mub[j] += -(h1[b] - h0[b]) * wchi + h1[b] * cchi;
+      }
+    }
+    // M = sum_a phi_a diag(D_a) chi at phi^{n+1}
+    R p1b[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      R acc = R(0);
+#pragma unroll
+      for (int i = 0; i < NC; ++i)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc += Mb[i][k] * p.D[b][i] * p.chi[i][k];
+      p1b[b] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      R acc = R(0);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) acc += Mb[i][k] * php[N - 1] * p.chi[i][k];
+      gpart[G_D0 + i] = (double)acc;
+    }
+    // h chains
+    R p0b[N];
+#pragma unroll
+    for (int g = 0; g < N; ++g) {
+      R a1 = R(0), a0 = R(0);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        a1 += h1b[b] * dh<N, R>(php, b, g);
+        a0 += h0b[b] * dh<N, R>(ph0, b, g);
+      }
+      p1b[g] += a1;
+      p0b[g] = a0;
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) lmu0[i * p.cells + P] += mub[i];
+#pragma unroll
+    for (int a = 0; a < D; ++a) lu0[a * p.cells + P] = Ub[a];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      t_phi1[b * p.cells + P] = p1b[b];
+      lphi0[b * p.cells + P] = p0b[b];
+    }
+  }
+  block_partials(gpart, part);
+}
+
+// ---------------------------------------------------------------------------
+// 4. projection and the local phase-field terms
+// ---------------------------------------------------------------------------
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_adj_phi1(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ mu0,
+           const R* __restrict__ lphi1, const R* __restrict__ t_phil, const R* __restrict__ t_phi1,
+           R* __restrict__ lphi0, R* __restrict__ lmu0, R* __restrict__ rbar, R tshift,
+           double* __restrict__ part) {
+  const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
+  double gpart[NG] = {0, 0, 0, 0, 0, 0};
+  if (P < p.cells) {
+    int x, y, z;
+    cell_coords(P, p.sy, p.sz, p.n[0], p.n[1], x, y, z);
+    R v[N][3][3][3];
+    load_stencil<D, N, R>(p, phi0, x, y, z, v);
+    const unsigned active = active_of<D, N, R>(v);
+    R pb[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) pb[b] = lphi1[b * p.cells + P] + t_phi1[b * p.cells + P];
+    pb[N - 1] += t_phil[P];
+    R p0b[N], Rb[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      p0b[b] = lphi0[b * p.cells + P];
+      Rb[b] = R(0);
+    }
+    if (__builtin_popcount(active) <= 1) {
+#pragma unroll
+      for (int b = 0; b < N; ++b) p0b[b] += pb[b];
+    } else {
+      R Rv[N], vv[N], out[N], theta;
+      pf_rhs<D, N, NC, R>(p, v, mu0, x, y, z, tshift, Rv);
+#pragma unroll
+      for (int b = 0; b < N; ++b) vv[b] = v[b][1][1][1] + p.rate * Rv[b];
+      project_masked<N, R>(active, vv, out, theta);
+      unsigned supp = 0u;
+      int ns = 0;
+      R mean = R(0);
+#pragma unroll
+      for (int b = 0; b < N; ++b)
+        if (((active >> b) & 1u) && vv[b] - theta > R(0)) {
+          supp |= 1u << b;
+          ++ns;
+          mean += pb[b];
+        }
+      mean = mean / R(ns);
+      R vb[N], taub = R(0);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        vb[b] = ((supp >> b) & 1u) ? pb[b] - mean : R(0);
+        p0b[b] += vb[b];
+        Rb[b] = p.rate * vb[b];
+        taub += vb[b] * Rv[b] * (-p.rate / p.tau_pf);
+      }
+      gpart[G_TAU] = (double)taub;
+      // local terms: -dW/dphi / eps and -sum psi dh/dphi
+      R ph[N], m[NC];
+#pragma unroll
+      for (int b = 0; b < N; ++b) ph[b] = v[b][1][1][1];
+#pragma unroll
+      for (int i = 0; i < NC; ++i) m[i] = mu0[i * p.cells + P];
+#pragma unroll
+      for (int al = 0; al < N; ++al)
+#pragma unroll
+        for (int be = 0; be < N; ++be) {
+          if (be == al) continue;
+          if (p.potential == 0) {
+            p0b[be] += -Rb[al] * R(1.6211389382774044) * p.gamma[al][be] / p.eps;  // 16 / pi^2
+          } else {
+            p0b[al] += -Rb[al] * R(18) * p.gamma[al][be] * ph[be] * ph[be] / p.eps;
+            p0b[be] += -Rb[al] * R(36) * p.gamma[al][be] * ph[al] * ph[be] / p.eps;
+          }
+        }
+      const R tdev = (p.G != R(0)) ? p.G * (R((p.pull_axis == 0) ? x : (p.pull_axis == 1 ? y : z)) - tshift)
+                                   : p.tdev_iso;
+      R ps[N], C[N][NC];
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        R r = R(0);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          R chimu = R(0);
+#pragma unroll
+          for (int j = 0; j < NC; ++j) chimu += p.chi[i][j] * m[j];
+          r += -R(0.5) * m[i] * chimu - m[i] * p.c0[b][i];
+          C[b][i] = p.c0[b][i] + chimu;
+        }
+        ps[b] = r + p.dS[b] * tdev;
+      }
+      R mub[NC];
+#pragma unroll
+      for (int i = 0; i < NC; ++i) mub[i] = R(0);
+#pragma unroll
+      for (int al = 0; al < N; ++al)
+#pragma unroll
+        for (int be = 0; be < N; ++be) {
+          const R d1 = dh<N, R>(ph, be, al);
+#pragma unroll
+          for (int i = 0; i < NC; ++i) mub[i] += Rb[al] * d1 * C[be][i];
+#pragma unroll
+          for (int g = 0; g < N; ++g) p0b[g] += -Rb[al] * ps[be] * d2h<N, R>(ph, be, al, g);
+        }
+#pragma unroll
+      for (int i = 0; i < NC; ++i) lmu0[i * p.cells + P] += mub[i];
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      lphi0[b * p.cells + P] = p0b[b];
+      rbar[b * p.cells + P] = Rb[b];
+    }
+  }
+  block_partials(gpart, part);
+}
+
+// ---------------------------------------------------------------------------
+// 5. face fluxes and cell-centre terms of the gradient energy, gathered
+// ---------------------------------------------------------------------------
+
+// position along one axis of a face owner or cell-term centre: periodic axes
+// wrap, positions outside a wall do not exist
+__device__ __forceinline__ bool owner_coord(int v, int n, int per, int& out) {
+  if (v >= 0 && v < n) { out = v; return true; }
+  if (!per) return false;
+  out = ((v % n) + n) % n;
+  return true;
+}
+
+// Reverse of one face flux J_a (left cell L, right cell L + e_a), seeded with
+// Jb[phase].  Roles: 0 L, 1 R, then per tangential axis b (in order): L-e_b,
+// L+e_b, R-e_b, R+e_b.  rc: role coordinates (walls mirrored, wraps applied);
+// contrib: adjoint of phi at each role.  dd: derivative in delta (pairs with
+// delta != 0).
+template <int D, int N, class R>
+__device__ __forceinline__ void face_vjp(const KP<R>& p, const R* __restrict__ phi, const int (&Lc)[3],
+                                         int a, const R (&Jb)[N], int (&rc)[2 + 4 * (D - 1)][3],
+                                         R (&contrib)[2 + 4 * (D - 1)][N], R& dd) {
+  constexpr int NR = 2 + 4 * (D - 1);
+  int o[NR][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) o[r][0] = o[r][1] = o[r][2] = 0;
+  o[1][a] = 1;
+  {
+    int r = 2;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (b == a) continue;
+      o[r][b] = -1;
+      o[r + 1][b] = 1;
+      o[r + 2][a] = 1;
+      o[r + 2][b] = -1;
+      o[r + 3][a] = 1;
+      o[r + 3][b] = 1;
+      r += 4;
+    }
+  }
+  R ph[NR][N];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      rc[r][e] = (e < D) ? nb_field(Lc[e], o[r][e], p.n[e], p.per[e]) : 0;
+    const int64_t j = (int64_t)rc[r][2] * p.sz + (int64_t)rc[r][1] * p.sy + rc[r][0];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      ph[r][b] = phi[b * p.cells + j];
+      contrib[r][b] = R(0);
+    }
+  }
+  const R idx = R(1) / p.dx, ih2 = R(0.5) / p.dx;
+  R pf[N], gr[N][D];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    pf[b] = R(0.5) * (ph[0][b] + ph[1][b]);
+    int r = 2;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      if (e == a) {
+        gr[b][e] = (ph[1][b] - ph[0][b]) * idx;
+      } else {
+        gr[b][e] = R(0.5) * ((ph[r + 1][b] - ph[r][b]) * ih2 + (ph[r + 3][b] - ph[r + 2][b]) * ih2);
+        r += 4;
+      }
+    }
+  }
+  R pfb[N], grb[N][D];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    pfb[b] = R(0);
+#pragma unroll
+    for (int e = 0; e < D; ++e) grb[b][e] = R(0);
+  }
+  dd = R(0);
+#pragma unroll
+  for (int al = 0; al < N; ++al)
+#pragma unroll
+    for (int be = al + 1; be < N; ++be) {
+      if (Jb[al] == R(0) && Jb[be] == R(0)) continue;
+      R q[D], g[D];
+#pragma unroll
+      for (int e = 0; e < D; ++e) q[e] = pf[al] * gr[be][e] - pf[be] * gr[al][e];
+      dAdq<D, R, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, g);
+      pfb[be] += -Jb[al] * g[a];
+      pfb[al] += Jb[be] * g[a];
+      R gbv[D];
+#pragma unroll
+      for (int e = 0; e < D; ++e) gbv[e] = R(0);
+      gbv[a] = -Jb[al] * pf[be] + Jb[be] * pf[al];
+      R qb[D], ddl;
+      dAdq_vjp<D, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, gbv, qb, ddl);
+      if (p.delta[al][be] != R(0)) dd += ddl;
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        pfb[al] += qb[e] * gr[be][e];
+        pfb[be] -= qb[e] * gr[al][e];
+        grb[be][e] += qb[e] * pf[al];
+        grb[al][e] -= qb[e] * pf[be];
+      }
+    }
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    contrib[0][b] += R(0.5) * pfb[b] - grb[b][a] * idx;
+    contrib[1][b] += R(0.5) * pfb[b] + grb[b][a] * idx;
+    int r = 2;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      if (e == a) continue;
+      const R gcb = R(0.5) * grb[b][e] * ih2;
+      contrib[r][b] -= gcb;
+      contrib[r + 1][b] += gcb;
+      contrib[r + 2][b] -= gcb;
+      contrib[r + 3][b] += gcb;
+      r += 4;
+    }
+  }
+}
+
+// Reverse of the cell-centre term at P seeded with cb = -eps Rbar(P).
+// Roles: 0 P, then per axis b: P-e_b, P+e_b.
+template <int D, int N, class R>
+__device__ __forceinline__ void cell_vjp(const KP<R>& p, const R* __restrict__ phi, const int (&Pc)[3],
+                                         const R (&cb)[N], int (&rc)[1 + 2 * D][3],
+                                         R (&contrib)[1 + 2 * D][N], R& dd) {
+  constexpr int NR = 1 + 2 * D;
+  R ph[NR][N];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      int off = 0;
+      if (r > 0 && e == (r - 1) / 2) off = ((r - 1) % 2) ? 1 : -1;
+      rc[r][e] = (e < D) ? nb_field(Pc[e], off, p.n[e], p.per[e]) : 0;
+    }
+    const int64_t j = (int64_t)rc[r][2] * p.sz + (int64_t)rc[r][1] * p.sy + rc[r][0];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      ph[r][b] = phi[b * p.cells + j];
+      contrib[r][b] = R(0);
+    }
+  }
+  const R ih2 = R(0.5) / p.dx;
+  R gc[N][D], gcb[N][D], phb[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    phb[b] = R(0);
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      gc[b][e] = (ph[2 + 2 * e][b] - ph[1 + 2 * e][b]) * ih2;
+      gcb[b][e] = R(0);
+    }
+  }
+  dd = R(0);
+#pragma unroll
+  for (int al = 0; al < N; ++al)
+#pragma unroll
+    for (int be = al + 1; be < N; ++be) {
+      if (cb[al] == R(0) && cb[be] == R(0)) continue;
+      R q[D], g[D];
+#pragma unroll
+      for (int e = 0; e < D; ++e) q[e] = ph[0][al] * gc[be][e] - ph[0][be] * gc[al][e];
+      dAdq<D, R, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, g);
+      R gbv[D];
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        gbv[e] = cb[al] * gc[be][e] - cb[be] * gc[al][e];
+        gcb[be][e] += cb[al] * g[e];
+        gcb[al][e] -= cb[be] * g[e];
+      }
+      R qb[D], ddl;
+      dAdq_vjp<D, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, gbv, qb, ddl);
+      if (p.delta[al][be] != R(0)) dd += ddl;
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        phb[al] += qb[e] * gc[be][e];
+        phb[be] -= qb[e] * gc[al][e];
+        gcb[be][e] += qb[e] * ph[0][al];
+        gcb[al][e] -= qb[e] * ph[0][be];
+      }
+    }
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    contrib[0][b] += phb[b];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      contrib[1 + 2 * e][b] -= gcb[b][e] * ih2;
+      contrib[2 + 2 * e][b] += gcb[b][e] * ih2;
+    }
+  }
+}
+
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_adj_phi2(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar, R* __restrict__ lphi0,
+           double* __restrict__ part) {
+  const int64_t X = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
+  double gpart[NG] = {0, 0, 0, 0, 0, 0};
+  if (X < p.cells) {
+    int xc[3];
+    cell_coords(X, p.sy, p.sz, p.n[0], p.n[1], xc[0], xc[1], xc[2]);
+    R acc[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) acc[b] = R(0);
+    R ddown = R(0);
+    auto rb_at = [&](const int (&c)[3], R (&out)[N]) {
+      const int64_t j = (int64_t)c[2] * p.sz + (int64_t)c[1] * p.sy + c[0];
+#pragma unroll
+      for (int b = 0; b < N; ++b) out[b] = rbar[b * p.cells + j];
+    };
+    // ---- faces ----
+    constexpr int NR = 2 + 4 * (D - 1);
+    for (int a = 0; a < D; ++a) {
+      int64_t seen[NR];
+      int nseen = 0;
+      // role offsets of a face relative to its left cell
+      int ro[NR][3];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) ro[r][0] = ro[r][1] = ro[r][2] = 0;
+      ro[1][a] = 1;
+      {
+        int r = 2;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          if (b == a) continue;
+          ro[r][b] = -1;
+          ro[r + 1][b] = 1;
+          ro[r + 2][a] = 1;
+          ro[r + 2][b] = -1;
+          ro[r + 3][a] = 1;
+          ro[r + 3][b] = 1;
+          r += 4;
+        }
+      }
+      for (int r = 0; r < NR; ++r) {
+        int Lc[3] = {0, 0, 0}, Rc[3] = {0, 0, 0};
+        bool ok = true;
+#pragma unroll
+        for (int e = 0; e < D; ++e) ok = ok && owner_coord(xc[e] - ro[r][e], p.n[e], p.per[e], Lc[e]);
+        if (!ok) continue;
+#pragma unroll
+        for (int e = 0; e < D; ++e) Rc[e] = Lc[e];
+        if (!owner_coord(Lc[a] + 1, p.n[a], p.per[a], Rc[a])) continue;  // wall face
+        const int64_t Lj = (int64_t)Lc[2] * p.sz + (int64_t)Lc[1] * p.sy + Lc[0];
+        bool dup = false;
+        for (int i = 0; i < nseen; ++i) dup = dup || (seen[i] == Lj);
+        if (dup) continue;
+        seen[nseen++] = Lj;
+        R rl[N], rr[N], Jb[N];
+        rb_at(Lc, rl);
+        rb_at(Rc, rr);
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          Jb[b] = p.eps * (rl[b] - rr[b]) / p.dx;
+          any = any || (Jb[b] != R(0));
+        }
+        if (!any) continue;
+        int rc[NR][3];
+        R contrib[NR][N], dd;
+        face_vjp<D, N, R>(p, phi0, Lc, a, Jb, rc, contrib, dd);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          bool hit = true;
+#pragma unroll
+          for (int e = 0; e < D; ++e) hit = hit && (rc[q][e] == xc[e]);
+          if (hit)
+#pragma unroll
+            for (int b = 0; b < N; ++b) acc[b] += contrib[q][b];
+        }
+        if (Lj == X) ddown += dd;
+      }
+    }
+    // ---- cell-centre terms ----
+    {
+      constexpr int NC_R = 1 + 2 * D;
+      int64_t seen[NC_R];
+      int nseen = 0;
+      for (int r = 0; r < NC_R; ++r) {
+        int off[3] = {0, 0, 0};
+        if (r > 0) off[(r - 1) / 2] = ((r - 1) % 2) ? 1 : -1;
+        int Pc[3] = {0, 0, 0};
+        bool ok = true;
+#pragma unroll
+        for (int e = 0; e < D; ++e) ok = ok && owner_coord(xc[e] - off[e], p.n[e], p.per[e], Pc[e]);
+        if (!ok) continue;
+        const int64_t Pj = (int64_t)Pc[2] * p.sz + (int64_t)Pc[1] * p.sy + Pc[0];
+        bool dup = false;
+        for (int i = 0; i < nseen; ++i) dup = dup || (seen[i] == Pj);
+        if (dup) continue;
+        seen[nseen++] = Pj;
+        R rp[N], cbv[N];
+        rb_at(Pc, rp);
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          cbv[b] = -p.eps * rp[b];
+          any = any || (cbv[b] != R(0));
+        }
+        if (!any) continue;
+        int rc[NC_R][3];
+        R contrib[NC_R][N], dd;
+        cell_vjp<D, N, R>(p, phi0, Pc, cbv, rc, contrib, dd);
+#pragma unroll
+        for (int q = 0; q < NC_R; ++q) {
+          bool hit = true;
+#pragma unroll
+          for (int e = 0; e < D; ++e) hit = hit && (rc[q][e] == xc[e]);
+          if (hit)
+#pragma unroll
+            for (int b = 0; b < N; ++b) acc[b] += contrib[q][b];
+        }
+        if (Pj == X) ddown += dd;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b) lphi0[b * p.cells + X] += acc[b];
+    gpart[G_DELTA] = (double)ddown;
+  }
+  block_partials(gpart, part);
+}
+
+// Sum the per-block partials of the four kernels of a reverse step in a
+// fixed order and add them to the FP64 accumulators.
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_grad_accum(const double* __restrict__ part, int nparts, int nblocks, double* __restrict__ acc) {
+  __shared__ double sh[ADJ_BLOCK];
+  for (int i = 0; i < NG; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k)
+      for (int b = threadIdx.x; b < nblocks; b += ADJ_BLOCK)
+        s += part[((int64_t)k * nblocks + b) * NG + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = ADJ_BLOCK / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[i] += sh[0];
+    __syncthreads();
+  }
+}
+
+template <class R>
+__global__ void k_fill(R* __restrict__ a, int64_t n, R v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+}  // namespace gpf

@@ -62,6 +62,7 @@ template <class R> struct KP {
   int potential;          // 0 obstacle, 1 well
   int pull_axis, grav_axis;
   R dx, dt, eps, rate;    // rate = dt / (tau_pf eps)
+  R tau_pf;
   R gamma[3][3], delta[3][3];
   R chi[2][2], c0[3][2], dS[3];
   R D[3][2];
@@ -75,33 +76,73 @@ template <class R> struct KP {
 // Pointwise model functions.
 // ---------------------------------------------------------------------------
 
+// Forward-mode dual number: value and one directional derivative.  Used to
+// differentiate dA/dq (Hessian-vector products and the derivative in delta)
+// with the very code that evaluates it.
+template <class R> struct Dual {
+  R v, d;
+  __device__ __forceinline__ Dual() : v(R(0)), d(R(0)) {}
+  __device__ __forceinline__ Dual(R a) : v(a), d(R(0)) {}
+  __device__ __forceinline__ Dual(R a, R b) : v(a), d(b) {}
+};
+template <class R> __device__ __forceinline__ Dual<R> operator+(Dual<R> a, Dual<R> b) { return {a.v + b.v, a.d + b.d}; }
+template <class R> __device__ __forceinline__ Dual<R> operator-(Dual<R> a, Dual<R> b) { return {a.v - b.v, a.d - b.d}; }
+template <class R> __device__ __forceinline__ Dual<R> operator*(Dual<R> a, Dual<R> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <class R> __device__ __forceinline__ Dual<R> operator/(Dual<R> a, Dual<R> b) {
+  const R q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+template <class R> __device__ __forceinline__ Dual<R>& operator+=(Dual<R>& a, Dual<R> b) { a = a + b; return a; }
+template <class R> __device__ __forceinline__ R value_of(R x) { return x; }
+template <class R> __device__ __forceinline__ R value_of(Dual<R> x) { return x.v; }
+
 // dA/dq of the pair energy A(q) = gamma a_c(q)^2 |q|^2 with the cubic
 // anisotropy a_c = 1 - delta (3 - 4 sum q_a^4 / |q|^4) (2D: 1 + delta cos 4theta):
 //   dA/dq = 2 gamma a_c (a_c q + |q|^2 grad a_c),
 //   grad a_c = 16 delta (q_a^3 / |q|^4 - q_a sum q^4 / |q|^6);
-// a_c = 1 and grad a_c = 0 below |q|^2 = qmin2.
-template <int D, class R>
-__device__ __forceinline__ void dAdq(const R (&q)[D], R gamma, R delta, R qmin2, R (&out)[D]) {
-  R q2 = R(0), q4 = R(0);
+// a_c = 1 and grad a_c = 0 below |q|^2 = qmin2.  T is R or Dual<R>.
+template <int D, class T, class R>
+__device__ __forceinline__ void dAdq(const T (&q)[D], T gamma, T delta, R qmin2, T (&out)[D]) {
+  T q2 = T(R(0)), q4 = T(R(0));
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    R s = q[a] * q[a];
+    T s = q[a] * q[a];
     q2 += s;
     q4 += s * s;
   }
-  if (!(q2 > qmin2)) {
+  if (!(value_of(q2) > qmin2)) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) out[a] = R(2) * gamma * q[a];
+    for (int a = 0; a < D; ++a) out[a] = T(R(2)) * gamma * q[a];
     return;
   }
-  R inv = R(1) / q2;
-  R inv2 = inv * inv;
-  R ac = R(1) - delta * (R(3) - R(4) * q4 * inv2);
+  T inv = T(R(1)) / q2;
+  T inv2 = inv * inv;
+  T ac = T(R(1)) - delta * (T(R(3)) - T(R(4)) * q4 * inv2);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    R g = R(16) * delta * inv2 * (q[a] * q[a] * q[a] - q[a] * q4 * inv);
-    out[a] = R(2) * gamma * ac * (ac * q[a] + q2 * g);
+    T g = T(R(16)) * delta * inv2 * (q[a] * q[a] * q[a] - q[a] * q4 * inv);
+    out[a] = T(R(2)) * gamma * ac * (ac * q[a] + q2 * g);
   }
+}
+
+// H(q) w (H = d^2 A / dq^2, symmetric) and d(dA/dq)/d delta . w, by forward
+// mode through dAdq.
+template <int D, class R>
+__device__ __forceinline__ void dAdq_vjp(const R (&q)[D], R gamma, R delta, R qmin2, const R (&w)[D],
+                                         R (&Hw)[D], R& ddelta_w) {
+  Dual<R> qd[D], out[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) qd[a] = Dual<R>(q[a], w[a]);
+  dAdq<D, Dual<R>, R>(qd, Dual<R>(gamma), Dual<R>(delta), qmin2, out);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    Hw[a] = out[a].d;
+    qd[a] = Dual<R>(q[a]);
+  }
+  dAdq<D, Dual<R>, R>(qd, Dual<R>(gamma), Dual<R>(delta, R(1)), qmin2, out);
+  ddelta_w = R(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) ddelta_w += out[a].d * w[a];
 }
 
 // Interpolation h_a(phi): N = 2: phi^2 (3 - 2 phi); N = 3 adds 2 phi_0 phi_1 phi_2.
@@ -126,30 +167,47 @@ __device__ __forceinline__ R dh(const R (&ph)[N], int b, int a) {
   return r;
 }
 
-// Euclidean projection of v[0..m) onto the simplex {sum = 1, >= 0}
-// (sort descending, largest j with u_j - (sum_{i<=j} u_i - 1)/j > 0;
-// Held, Wolfe and Crowder 1974).  m <= 3: a three-element sorting network.
-template <class R>
-__device__ __forceinline__ void project_simplex(int m, R (&v)[3], R (&out)[3]) {
-  R u0 = v[0], u1 = (m > 1) ? v[1] : R(0), u2 = (m > 2) ? v[2] : R(0);
-  if (m > 1 && u1 > u0) { R t = u0; u0 = u1; u1 = t; }
-  if (m > 2) {
-    if (u2 > u1) { R t = u1; u1 = u2; u2 = t; }
-    if (u1 > u0) { R t = u0; u0 = u1; u1 = t; }
+// Euclidean projection onto the simplex {sum = 1, >= 0} of the entries of v
+// selected by `mask` (the others are set to 0): sort the selected values
+// descending, take the largest j with u_j - (sum_{i<=j} u_i - 1)/j > 0,
+// theta = (sum_{i<=j} u_i - 1)/j, result max(v - theta, 0) (Held, Wolfe and
+// Crowder 1974).  N <= 3: a sorting network on fixed-size arrays, unselected
+// entries sorted last.
+template <int N, class R>
+__device__ __forceinline__ void project_masked(unsigned mask, const R (&v)[N], R (&out)[N], R& theta) {
+  R u[3];
+  bool on[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    on[i] = (i < N) && ((mask >> i) & 1u);
+    u[i] = (i < N) ? v[i] : R(0);
   }
-  R csum = u0, theta = u0 - R(1);  // j = 1 always qualifies: u0 - (u0 - 1) = 1 > 0
-  if (m > 1) {
-    csum += u1;
-    R t = (csum - R(1)) / R(2);
-    if (u1 - t > R(0)) theta = t;
+  // descending by (selected, value)
+  auto cs = [&](int i, int j) {
+    const bool swap = (!on[i] && on[j]) || (on[i] == on[j] && u[j] > u[i]);
+    if (swap) {
+      R t = u[i]; u[i] = u[j]; u[j] = t;
+      bool b = on[i]; on[i] = on[j]; on[j] = b;
+    }
+  };
+  cs(0, 1);
+  cs(1, 2);
+  cs(0, 1);
+  R csum = u[0];
+  theta = u[0] - R(1);  // j = 1 always qualifies
+  if (on[1]) {
+    csum += u[1];
+    const R t = (csum - R(1)) / R(2);
+    if (u[1] - t > R(0)) theta = t;
   }
-  if (m > 2) {
-    csum += u2;
-    R t = (csum - R(1)) / R(3);
-    if (u2 - t > R(0)) theta = t;
+  if (on[2]) {
+    csum += u[2];
+    const R t = (csum - R(1)) / R(3);
+    if (u[2] - t > R(0)) theta = t;
   }
 #pragma unroll
-  for (int i = 0; i < 3; ++i) out[i] = (i < m && v[i] - theta > R(0)) ? v[i] - theta : R(0);
+  for (int i = 0; i < N; ++i)
+    out[i] = (((mask >> i) & 1u) && v[i] - theta > R(0)) ? v[i] - theta : R(0);
 }
 
 // Neighbour coordinate along one axis for field values: periodic axes wrap,

@@ -46,14 +46,10 @@ __device__ __forceinline__ R pull_f(const KP<R>& p, const R* __restrict__ fin, i
 // ---------------------------------------------------------------------------
 // Phase field: active set, right-hand side, projection.
 // ---------------------------------------------------------------------------
-// phi^{n+1} of cell (x, y, z) from phi^n on its 9 (2D) / 19 (3D) point
-// neighbourhood v[phase][dz+1][dy+1][dx+1] (walls mirrored, periodic axes
-// wrapped; the corners of the 3x3x3 cube are not used) and mu^n at the cell.
-template <int D, int N, int NC, class R>
-__device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N][3][3][3],
-                                                 const R* __restrict__ mu, int x, int y, int z,
-                                                 R tshift, R (&res)[N]) {
-  const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
+// Active set of a cell: bit b set when phase b is non-zero somewhere in the
+// 9/19-point neighbourhood v[phase][dz+1][dy+1][dx+1].
+template <int D, int N, class R>
+__device__ __forceinline__ unsigned active_of(const R (&v)[N][3][3][3]) {
   unsigned active = 0u;
 #pragma unroll
   for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
@@ -66,13 +62,20 @@ __device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N]
         for (int b = 0; b < N; ++b)
           if (v[b][dz + 1][dy + 1][dx + 1] > R(0)) active |= 1u << b;
       }
-  const int na = __builtin_popcount(active);
-  if (na <= 1) {  // bulk: phi unchanged
-#pragma unroll
-    for (int b = 0; b < N; ++b) res[b] = v[b][1][1][1];
-    return;
-  }
+  return active;
+}
 
+// Right-hand side R_a of Eq. (PhfGrand) (tau eps dphi_a/dt = R_a before the
+// constraint) for every phase, from phi^n on the neighbourhood v (walls
+// mirrored, periodic axes wrapped; the cube corners are not used) and mu^n:
+//   R_a = eps [div J_a - sum_b dA_ab/dq(q_ab) . grad phi_b] - dW/dphi_a / eps
+//         - sum_b psi^b dh_b/dphi_a,
+// J_a = -sum_b phi_b,f dA_ab/dq(q_ab,f) on faces (none on wall faces).
+template <int D, int N, int NC, class R>
+__device__ __forceinline__ void pf_rhs(const KP<R>& p, const R (&v)[N][3][3][3],
+                                       const R* __restrict__ mu, int x, int y, int z, R tshift,
+                                       R (&Rv)[N]) {
+  const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
   const int pos[3] = {x, y, z};
   const R idx = R(1) / p.dx;
   const R ih2 = R(0.5) / p.dx;
@@ -121,7 +124,7 @@ __device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N]
           R q[D], g[D];
 #pragma unroll
           for (int e = 0; e < D; ++e) q[e] = pf[al] * gf[be][e] - pf[be] * gf[al][e];
-          dAdq<D, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, g);
+          dAdq<D, R, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, g);
           J[al] -= pf[be] * g[a];
           J[be] += pf[al] * g[a];
         }
@@ -148,7 +151,7 @@ __device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N]
       R q[D], g[D];
 #pragma unroll
       for (int e = 0; e < D; ++e) q[e] = ph[al] * g0[be][e] - ph[be] * g0[al][e];
-      dAdq<D, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, g);
+      dAdq<D, R, R>(q, p.gamma[al][be], p.delta[al][be], p.qmin2, g);
 #pragma unroll
       for (int e = 0; e < D; ++e) {
         cell[al] += g[e] * g0[be][e];
@@ -175,9 +178,6 @@ __device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N]
     ps[b] = r + p.dS[b] * tdev;
   }
 
-  R vv[3] = {R(0), R(0), R(0)};
-  int which[3] = {0, 0, 0};
-  int cnt = 0;
 #pragma unroll
   for (int al = 0; al < N; ++al) {
     R dW = R(0);
@@ -192,30 +192,31 @@ __device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N]
     R drive = R(0);
 #pragma unroll
     for (int be = 0; be < N; ++be) drive += ps[be] * dh<N, R>(ph, be, al);
-    const R Ra = p.eps * (div[al] - cell[al]) - dW / p.eps - drive;
-    if ((active >> al) & 1u) {
-      vv[cnt] = ph[al] + p.rate * Ra;
-      which[cnt] = al;
-      ++cnt;
-    }
+    Rv[al] = p.eps * (div[al] - cell[al]) - dW / p.eps - drive;
   }
-  R out[3];
-  project_simplex<R>(cnt, vv, out);
-#pragma unroll
-  for (int b = 0; b < N; ++b) res[b] = R(0);
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-    if (j < cnt) {
-#pragma unroll
-      for (int b = 0; b < N; ++b)
-        if (which[j] == b) res[b] = out[j];
-    }
 }
 
+// phi^{n+1} of a cell from its neighbourhood v and mu^n: unchanged when one
+// phase is active, else the projection of phi + dt/(tau eps) R over the
+// active phases onto the simplex.  theta returns the projection's shift.
+template <int D, int N, int NC, class R>
+__device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N][3][3][3],
+                                                 const R* __restrict__ mu, int x, int y, int z,
+                                                 R tshift, R (&res)[N]) {
+  const unsigned active = active_of<D, N, R>(v);
+  if (__builtin_popcount(active) <= 1) {  // bulk: phi unchanged
+#pragma unroll
+    for (int b = 0; b < N; ++b) res[b] = v[b][1][1][1];
+    return;
+  }
+  R Rv[N], vv[N];
+  pf_rhs<D, N, NC, R>(p, v, mu, x, y, z, tshift, Rv);
+#pragma unroll
+  for (int b = 0; b < N; ++b) vv[b] = v[b][1][1][1] + p.rate * Rv[b];
+  R theta;
+  project_masked<N, R>(active, vv, res, theta);
+}
 
-// ---------------------------------------------------------------------------
-// Chemical potential + lattice Boltzmann (forces, moments, BGK + Guo, pull
-// streaming).
 // ---------------------------------------------------------------------------
 // mu^{n+1}, U^n and the post-collision populations of cell (x, y, z), given
 // the values it reads around itself:

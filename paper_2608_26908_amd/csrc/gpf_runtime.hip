@@ -17,7 +17,7 @@
 #include <vector>
 
 #include "../../include/gpf.h"
-#include "gpf_kernels.hpp"
+#include "gpf_adjoint.hpp"
 
 namespace {
 
@@ -31,6 +31,11 @@ struct Ops;
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
+};
+
+// one full state: phi [N], mu [nc], U [dim], stored populations f* [Q]
+struct StateBuf {
+  DevBuf phi, mu, u, f;
 };
 
 }  // namespace
@@ -52,6 +57,14 @@ struct gpf_ctx {
   DevBuf badstep;   // health: smallest failing step
   const Ops* ops = nullptr;
   std::string err;
+  // adjoint: checkpoints every rec_every steps from step rec_start
+  int64_t rec_every = 0, rec_start = 0;
+  std::vector<StateBuf> ckpt;
+  std::vector<StateBuf> tape;      // rec_every + 1 recomputed states of one segment
+  StateBuf lam[2];                 // adjoint state (phi, mu, U, post-streaming f)
+  DevBuf t_phil, t_mu, t_w, t_phi1, t_rbar, t_part, t_acc;
+  int lam_cur = 0;                 // lam[lam_cur] holds the adjoint of the earliest state reached
+  bool have_adjoint = false;
 };
 
 namespace {
@@ -124,6 +137,7 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
   k.dt = (R)p.dt;
   k.eps = (R)p.eps;
   k.rate = (R)(p.dt / (p.tau_pf * p.eps));
+  k.tau_pf = (R)p.tau_pf;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
       k.gamma[a][b] = (R)p.gamma[a][b];
@@ -169,6 +183,9 @@ struct Ops {
   int (*write)(gpf_ctx*, int);          // from scratch
   int (*reduce)(gpf_ctx*, int, double*);
   int (*read_native)(gpf_ctx*, int, void*);
+  int (*adjoint)(gpf_ctx*, const double*, double*);
+  int (*copy_state)(gpf_ctx*, const StateBuf&, const StateBuf&);
+  int (*lam_read)(gpf_ctx*, int, double*);
 };
 
 inline unsigned lin_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -188,19 +205,25 @@ struct Impl {
     return GPF_OK;
   }
 
+  struct SP {
+    R *phi, *mu, *u, *f;
+  };
+  static SP sp(StateBuf& s) { return SP{P(s.phi), P(s.mu), P(s.u), P(s.f)}; }
+  static SP cur(gpf_ctx* c, int s) { return SP{P(c->phi[s]), P(c->mu[s]), P(c->u[s]), P(c->f[s])}; }
+
   template <int TY>
-  static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, int s, int t, R ts, int zc, hipEvent_t* ev) {
+  static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& in, const SP& out, R ts, int zc,
+                          hipEvent_t* ev) {
     constexpr int TX = 64;
     const int tiles_x = (int)((c->n[0] + TX - 1) / TX), tiles_y = (int)((c->n[1] + TY - 1) / TY);
     const int tiles_z = (D == 3) ? (int)((c->n[2] + zc - 1) / zc) : 1;
     const dim3 grid((unsigned)tiles_x * (unsigned)tiles_y * (unsigned)tiles_z), block(TX * TY);
     if (ev) (void)hipEventRecord(ev[0], c->stream);
-    hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, P(c->phi[s]),
-                       P(c->mu[s]), P(c->phi[t]), ts, tiles_x, tiles_y, zc);
+    hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, in.phi, in.mu,
+                       out.phi, ts, tiles_x, tiles_y, zc);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
-    hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, P(c->phi[s]),
-                       P(c->phi[t]), P(c->mu[s]), P(c->u[s]), P(c->f[s]), P(c->mu[t]), P(c->u[t]),
-                       P(c->f[t]), tiles_x, tiles_y, zc);
+    hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, in.phi, out.phi,
+                       in.mu, in.u, in.f, out.mu, out.u, out.f, tiles_x, tiles_y, zc);
     if (ev) (void)hipEventRecord(ev[2], c->stream);
   }
 
@@ -217,7 +240,7 @@ struct Impl {
     for (int64_t it = 0; it < nsteps; ++it) {
       const int s = c->cur, t = 1 - c->cur;
       const R ts = (R)tshift(c, c->step);
-      launch_step<4>(c, k, s, t, ts, kZChunk, kernel_ms ? ev : nullptr);
+      launch_step<4>(c, k, cur(c, s), cur(c, t), ts, kZChunk, kernel_ms ? ev : nullptr);
       HIP_OR_FAIL(c, hipGetLastError());
       if (kernel_ms) {
         HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
@@ -231,6 +254,10 @@ struct Impl {
       c->step += 1;
       if (H > 0 && (c->step % H == 0 || it == nsteps - 1)) {
         int rc = health(c);
+        if (rc) return rc;
+      }
+      if (c->rec_every > 0 && (c->step - c->rec_start) % c->rec_every == 0) {
+        int rc = save_ckpt(c);
         if (rc) return rc;
       }
     }
@@ -352,8 +379,154 @@ struct Impl {
     return GPF_OK;
   }
 
+  // ---------------- adjoint ----------------
+  static int alloc_state(gpf_ctx* c, StateBuf& s) {
+    const size_t cs = (size_t)c->cells * sizeof(R);
+    int rc = dev_alloc(c, s.phi, N * cs);
+    if (!rc) rc = dev_alloc(c, s.mu, NC * cs);
+    if (!rc) rc = dev_alloc(c, s.u, D * cs);
+    if (!rc) rc = dev_alloc(c, s.f, gpf::Lat<D>::Q * cs);
+    return rc;
+  }
+  static int copy_state(gpf_ctx* c, const StateBuf& dst, const StateBuf& src) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(dst.phi.ptr, src.phi.ptr, dst.phi.bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(dst.mu.ptr, src.mu.ptr, dst.mu.bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(dst.u.ptr, src.u.ptr, dst.u.bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(dst.f.ptr, src.f.ptr, dst.f.bytes, hipMemcpyDeviceToDevice, c->stream));
+    return GPF_OK;
+  }
+  static int save_ckpt(gpf_ctx* c) {
+    StateBuf s;
+    int rc = alloc_state(c, s);
+    if (rc) return rc;
+    c->ckpt.push_back(s);
+    StateBuf cur_s;
+    cur_s.phi = c->phi[c->cur];
+    cur_s.mu = c->mu[c->cur];
+    cur_s.u = c->u[c->cur];
+    cur_s.f = c->f[c->cur];
+    return copy_state(c, s, cur_s);
+  }
+  static void fill(gpf_ctx* c, DevBuf& b, int64_t n) {
+    hipLaunchKernelGGL((gpf::k_fill<R>), dim3(lin_blocks(n, 256)), dim3(256), 0, c->stream, P(b), n, R(0));
+  }
+
+  // one reverse step: lam_in = adjoint of X^{n+1} -> lam_out = adjoint of X^n
+  static void reverse_step(gpf_ctx* c, const gpf::KP<R>& k, StateBuf& x0, StateBuf& x1, int64_t n,
+                           StateBuf& li, StateBuf& lo) {
+    const unsigned nb = lin_blocks(c->cells, gpf::ADJ_BLOCK);
+    double* part = static_cast<double*>(c->t_part.ptr);
+    const int64_t pstride = (int64_t)nb * gpf::NG;
+    const dim3 g(nb), b(gpf::ADJ_BLOCK);
+    hipLaunchKernelGGL((gpf::k_adj_lbm<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.f), P(x1.phi), P(x1.mu),
+                       P(li.f), P(li.u), P(lo.f), P(c->t_phil), P(c->t_mu), part);
+    hipLaunchKernelGGL((gpf::k_adj_w<D, N, NC, R>), g, b, 0, c->stream, k, P(x1.phi), P(li.mu), P(c->t_mu),
+                       P(c->t_w), P(lo.mu));
+    hipLaunchKernelGGL((gpf::k_adj_mu<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(x1.phi), P(x0.mu),
+                       P(x1.mu), P(x0.u), P(c->t_w), P(lo.mu), P(lo.u), P(c->t_phi1), P(lo.phi),
+                       part + pstride);
+    hipLaunchKernelGGL((gpf::k_adj_phi1<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(x0.mu), P(li.phi),
+                       P(c->t_phil), P(c->t_phi1), P(lo.phi), P(lo.mu), P(c->t_rbar),
+                       (R)tshift(c, n), part + 2 * pstride);
+    hipLaunchKernelGGL((gpf::k_adj_phi2<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(c->t_rbar),
+                       P(lo.phi), part + 3 * pstride);
+    hipLaunchKernelGGL(gpf::k_grad_accum, dim3(1), dim3(gpf::ADJ_BLOCK), 0, c->stream,
+                       static_cast<const double*>(c->t_part.ptr), 4, (int)nb,
+                       static_cast<double*>(c->t_acc.ptr));
+  }
+
+  // seed: dL/dphi at the current (final) state, FP64 host, N * cells values
+  static int adjoint(gpf_ctx* c, const double* seed, double* grads) {
+    const int64_t K = c->rec_every;
+    const int64_t total = c->step - c->rec_start;
+    if (K <= 0 || total <= 0 || c->ckpt.empty())
+      return fail(c, GPF_ERR_STATE, "nothing recorded: call gpf_record before stepping");
+    const size_t cs = (size_t)c->cells * sizeof(R);
+    int rc = GPF_OK;
+    if (!c->lam[0].phi.ptr) {
+      for (int i = 0; i < 2 && !rc; ++i) rc = alloc_state(c, c->lam[i]);
+      const unsigned nb = lin_blocks(c->cells, gpf::ADJ_BLOCK);
+      if (!rc) rc = dev_alloc(c, c->t_phil, cs);
+      if (!rc) rc = dev_alloc(c, c->t_mu, NC * cs);
+      if (!rc) rc = dev_alloc(c, c->t_w, NC * cs);
+      if (!rc) rc = dev_alloc(c, c->t_phi1, N * cs);
+      if (!rc) rc = dev_alloc(c, c->t_rbar, N * cs);
+      if (!rc) rc = dev_alloc(c, c->t_part, (size_t)4 * nb * gpf::NG * sizeof(double));
+      if (!rc) rc = dev_alloc(c, c->t_acc, gpf::NG * sizeof(double));
+      if (rc) return rc;
+    }
+    while ((int64_t)c->tape.size() < K) {
+      StateBuf s;
+      if ((rc = alloc_state(c, s))) return rc;
+      c->tape.push_back(s);
+    }
+    gpf::KP<R> k = make_kp<R>(c);
+    // lam^N = (seed, 0, 0, 0)
+    StateBuf* li = &c->lam[0];
+    StateBuf* lo = &c->lam[1];
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->scratch.ptr, seed, (size_t)N * c->cells * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL((gpf::k_from_double<R>), dim3(lin_blocks(N * c->cells, 256)), dim3(256), 0,
+                       c->stream, static_cast<const double*>(c->scratch.ptr), P(li->phi), N * c->cells);
+    fill(c, li->mu, NC * c->cells);
+    fill(c, li->u, D * c->cells);
+    fill(c, li->f, gpf::Lat<D>::Q * c->cells);
+    hipLaunchKernelGGL((gpf::k_fill<double>), dim3(1), dim3(gpf::NG), 0, c->stream,
+                       static_cast<double*>(c->t_acc.ptr), (int64_t)gpf::NG, 0.0);
+    const int64_t nseg = (total + K - 1) / K;
+    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+      const int64_t n0 = c->rec_start + sgi * K;
+      const int64_t len = std::min<int64_t>(K, total - sgi * K);
+      // recompute the segment: tape slot j holds X^{n0 + j}; slot 0 is the checkpoint
+      auto slot = [&](int64_t j) -> StateBuf& { return j == 0 ? c->ckpt[sgi] : c->tape[j - 1]; };
+      for (int64_t j = 0; j < len - 1; ++j)
+        launch_step<4>(c, k, sp(slot(j)), sp(slot(j + 1)), (R)tshift(c, n0 + j), 8, nullptr);
+      // X^{n0 + len} is the next checkpoint or, for the last segment, the current state
+      StateBuf endst;
+      if (sgi + 1 < (int64_t)c->ckpt.size()) {
+        endst = c->ckpt[sgi + 1];
+      } else {
+        endst.phi = c->phi[c->cur];
+        endst.mu = c->mu[c->cur];
+        endst.u = c->u[c->cur];
+        endst.f = c->f[c->cur];
+      }
+      for (int64_t j = len - 1; j >= 0; --j) {
+        StateBuf& x1 = (j + 1 == len) ? endst : slot(j + 1);
+        reverse_step(c, k, slot(j), x1, n0 + j, *li, *lo);
+        std::swap(li, lo);
+      }
+      HIP_OR_FAIL(c, hipGetLastError());
+    }
+    c->lam_cur = (li == &c->lam[0]) ? 0 : 1;
+    c->have_adjoint = true;
+    HIP_OR_FAIL(c, hipMemcpyAsync(grads, c->t_acc.ptr, gpf::NG * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return GPF_OK;
+  }
+
+  // adjoint of the recorded initial state, field by field, as FP64
+  static int lam_read(gpf_ctx* c, int field, double* host) {
+    StateBuf& l = c->lam[c->lam_cur];
+    const R* src = nullptr;
+    int64_t cnt = 0;
+    switch (field) {
+      case GPF_PHI: src = P(l.phi); cnt = N * c->cells; break;
+      case GPF_MU: src = P(l.mu); cnt = NC * c->cells; break;
+      case GPF_U: src = P(l.u); cnt = D * c->cells; break;
+      case GPF_F: src = P(l.f); cnt = gpf::Lat<D>::Q * c->cells; break;
+      default: return fail(c, GPF_ERR_ARG, "field %d has no adjoint", field);
+    }
+    hipLaunchKernelGGL((gpf::k_to_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, src,
+                       static_cast<double*>(c->scratch.ptr), cnt);
+    HIP_OR_FAIL(c, hipMemcpyAsync(host, c->scratch.ptr, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return GPF_OK;
+  }
+
   static const Ops* ops() {
-    static const Ops o = {&step, &read, &write, &reduce, &read_native};
+    static const Ops o = {&step, &read, &write, &reduce, &read_native, &adjoint, &copy_state, &lam_read};
     return &o;
   }
 };
@@ -535,6 +708,25 @@ void free_all(gpf_ctx* c) {
   dev_release(c, c->partial);
   dev_release(c, c->redout);
   dev_release(c, c->badstep);
+  auto rel = [&](StateBuf& s) {
+    dev_release(c, s.phi);
+    dev_release(c, s.mu);
+    dev_release(c, s.u);
+    dev_release(c, s.f);
+  };
+  for (auto& s : c->ckpt) rel(s);
+  for (auto& s : c->tape) rel(s);
+  c->ckpt.clear();
+  c->tape.clear();
+  rel(c->lam[0]);
+  rel(c->lam[1]);
+  dev_release(c, c->t_phil);
+  dev_release(c, c->t_mu);
+  dev_release(c, c->t_w);
+  dev_release(c, c->t_phi1);
+  dev_release(c, c->t_rbar);
+  dev_release(c, c->t_part);
+  dev_release(c, c->t_acc);
 }
 
 int set_named(gpf_ctx* c, gpf_params& p, const char* name, double v) {
@@ -698,6 +890,83 @@ int gpf_set_param(gpf_ctx* c, const char* name, double value) {
   if (rc) return rc;
   c->prm = p;
   return GPF_OK;
+}
+
+int gpf_record(gpf_ctx* c, int64_t checkpoint_every) {
+  if (!c) return GPF_ERR_ARG;
+  if (checkpoint_every < 1) return fail(c, GPF_ERR_ARG, "checkpoint_every must be >= 1");
+  (void)hipStreamSynchronize(c->stream);
+  auto rel = [&](StateBuf& s) {
+    dev_release(c, s.phi);
+    dev_release(c, s.mu);
+    dev_release(c, s.u);
+    dev_release(c, s.f);
+  };
+  for (auto& s : c->ckpt) rel(s);
+  c->ckpt.clear();
+  if ((int64_t)c->tape.size() > checkpoint_every) {
+    for (auto& s : c->tape) rel(s);
+    c->tape.clear();
+  }
+  c->rec_every = checkpoint_every;
+  c->rec_start = c->step;
+  c->have_adjoint = false;
+  StateBuf s;
+  const size_t cs = (size_t)c->cells * c->esize;
+  int rc = dev_alloc(c, s.phi, c->N * cs);
+  if (!rc) rc = dev_alloc(c, s.mu, c->nc * cs);
+  if (!rc) rc = dev_alloc(c, s.u, c->dim * cs);
+  if (!rc) rc = dev_alloc(c, s.f, c->Q * cs);
+  if (rc) return rc;
+  c->ckpt.push_back(s);
+  StateBuf cur_s;
+  cur_s.phi = c->phi[c->cur];
+  cur_s.mu = c->mu[c->cur];
+  cur_s.u = c->u[c->cur];
+  cur_s.f = c->f[c->cur];
+  rc = c->ops->copy_state(c, s, cur_s);
+  if (rc) return rc;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return GPF_OK;
+}
+
+static int grad_slot(const char* name) {
+  if (!std::strcmp(name, "delta")) return gpf::G_DELTA;
+  if (!std::strcmp(name, "tau_pf")) return gpf::G_TAU;
+  if (!std::strcmp(name, "D")) return gpf::G_D0;
+  if (!std::strcmp(name, "D1")) return gpf::G_D1;
+  if (!std::strcmp(name, "gbeta")) return gpf::G_GB0;
+  if (!std::strcmp(name, "gbeta1")) return gpf::G_GB1;
+  return -1;
+}
+
+int gpf_adjoint(gpf_ctx* c, const double* dL_dphi, size_t count, const char* const* names,
+                int32_t n_names, double* grads_out) {
+  if (!c || !dL_dphi || (n_names > 0 && (!names || !grads_out)) || n_names < 0) return GPF_ERR_ARG;
+  if (count != (size_t)c->N * (size_t)c->cells)
+    return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, (size_t)c->N * (size_t)c->cells);
+  if (n_names > gpf::NG) return fail(c, GPF_ERR_ARG, "at most %d parameters", gpf::NG);
+  int slots[gpf::NG];
+  for (int i = 0; i < n_names; ++i) {
+    slots[i] = names[i] ? grad_slot(names[i]) : -1;
+    if (slots[i] < 0) return fail(c, GPF_ERR_ARG, "unknown parameter '%s'", names[i] ? names[i] : "(null)");
+  }
+  double g[gpf::NG];
+  int rc = c->ops->adjoint(c, dL_dphi, g);
+  if (rc) return rc;
+  for (int i = 0; i < n_names; ++i) grads_out[i] = g[slots[i]];
+  return GPF_OK;
+}
+
+int gpf_adjoint_state(gpf_ctx* c, int32_t field, double* host_dst, size_t count) {
+  if (!c || !host_dst) return GPF_ERR_ARG;
+  if (!c->have_adjoint) return fail(c, GPF_ERR_STATE, "no adjoint computed yet");
+  const int comps = field == GPF_PHI ? c->N : field == GPF_MU ? c->nc : field == GPF_U ? c->dim
+                  : field == GPF_F ? c->Q : -1;
+  if (comps < 0) return fail(c, GPF_ERR_ARG, "field %d has no adjoint", field);
+  if (count != (size_t)comps * (size_t)c->cells)
+    return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, (size_t)comps * (size_t)c->cells);
+  return c->ops->lam_read(c, field, host_dst);
 }
 
 int64_t gpf_step_index(const gpf_ctx* c) { return c ? c->step : -1; }

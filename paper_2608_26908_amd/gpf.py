@@ -88,6 +88,9 @@ def lib():
         L.gpf_status_string.restype = ctypes.c_char_p
         L.gpf_status_string.argtypes = [ctypes.c_int]
         L.gpf_destroy.argtypes = [vp]
+        L.gpf_record.argtypes = [vp, i64]
+        L.gpf_adjoint.argtypes = [vp, dp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_char_p), i32, dp]
+        L.gpf_adjoint_state.argtypes = [vp, i32, dp, ctypes.c_size_t]
         _lib = L
     return _lib
 
@@ -252,3 +255,64 @@ class Sim:
 
     def set_param(self, name, value):
         self._check(lib().gpf_set_param(self._h, name.encode(), float(value)))
+
+    # -- adjoint -------------------------------------------------------------
+    def record(self, checkpoint_every):
+        self._check(lib().gpf_record(self._h, int(checkpoint_every)))
+
+    def adjoint(self, dL_dphi, names):
+        """FP64 dL/dp for the named parameters, given dL/dphi at the current
+        state; the adjoint of the recorded initial state is then available
+        from adjoint_state()."""
+        seed = np.ascontiguousarray(dL_dphi, dtype=np.float64).ravel()
+        arr = (ctypes.c_char_p * len(names))(*[n.encode() for n in names])
+        out = (ctypes.c_double * max(1, len(names)))()
+        self._check(lib().gpf_adjoint(self._h, seed.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      seed.size, arr, len(names), out))
+        return np.array(out[: len(names)])
+
+    def adjoint_state(self, field):
+        comps = self.components(field)
+        out = np.empty(comps * self.cells, dtype=np.float64)
+        self._check(lib().gpf_adjoint_state(self._h, FIELDS[field],
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            out.size))
+        return out.reshape((comps,) + self.shape)
+
+
+def _autograd_function():
+    import torch
+
+    class GPFRun(torch.autograd.Function):
+        """phi after n_steps of the coupled step as a differentiable function
+        of scalar parameters.  forward: restore the initial checkpoint, set
+        the parameters, record and run; backward: the hand-written adjoint
+        (gpf_adjoint), FP64 parameter gradients."""
+
+        @staticmethod
+        def forward(ctx, params, sim, initial, names, n_steps, checkpoint_every):
+            sim.restore(initial)
+            for name, v in zip(names, params.detach().cpu().tolist()):
+                sim.set_param(name, v)
+            sim.record(checkpoint_every)
+            sim.step(n_steps)
+            ctx.sim, ctx.names = sim, list(names)
+            return sim.read_device("phi")
+
+        @staticmethod
+        def backward(ctx, grad_phi):
+            g = ctx.sim.adjoint(grad_phi.detach().double().cpu().numpy(), ctx.names)
+            return torch.tensor(g, dtype=torch.float64), None, None, None, None, None
+
+    return GPFRun
+
+
+_GPFRun = None
+
+
+def gpf_run(params, sim, initial, names, n_steps, checkpoint_every):
+    """Differentiable run (torch.autograd): see GPFRun."""
+    global _GPFRun
+    if _GPFRun is None:
+        _GPFRun = _autograd_function()
+    return _GPFRun.apply(params, sim, initial, tuple(names), n_steps, checkpoint_every)
