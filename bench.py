@@ -56,6 +56,37 @@ def run_gpu(cfg, precision, steps, warmup):
                 mlups=cells * steps / (ms * 1e-3) / 1e6, solute=[float(v) for v in sol])
 
 
+def run_adjoint(cfg, precision, steps, K, names):
+    """Wall time of the forward run (recording checkpoints every K steps) and of
+    the reverse sweep (segment recompute + adjoint kernels), same stream."""
+    import numpy as np
+    import torch
+    from paper_2608_26908_amd.gpf import Sim
+    sim = Sim(cfg, precision=precision)
+    sim.step(2)  # warm-up of every kernel
+    torch.cuda.synchronize()
+    ck = sim.checkpoint()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    sim.restore(ck)
+    sim.record(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    seed = np.sin(np.arange(sim.N * sim.cells, dtype=np.float64))
+    t0 = time.perf_counter()
+    grads = sim.adjoint(seed, names)
+    t_adj = time.perf_counter() - t0
+    sim.close()
+    return dict(forward_ms=round(t_plain * 1e3, 2), forward_recording_ms=round(t_fwd * 1e3, 2),
+                adjoint_ms=round(t_adj * 1e3, 2), ratio=round(t_adj / t_plain, 3),
+                grads=dict(zip(names, [float(g) for g in grads])))
+
+
 def cpu_baseline(cfg, steps=2):
     """The FP64 oracle as it stands, on this host's cores, on a bounded
     sample of the same workload: the full grid, one untimed step, then
@@ -100,6 +131,7 @@ def main():
     ap.add_argument("--workload", default="dendrite3d")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a kernel of known "
                          "traffic to calibrate the HBM byte counters of a profiler run)")
@@ -171,6 +203,19 @@ def main():
                         "k_phi_ms": round(r64["k_phi_ms"], 4), "k_mulbm_ms": round(r64["k_mulbm_ms"], 4),
                         "roofline_frac": round(b64 * cells / (r64["k_mulbm_ms"] * 1e-3) / 1e9
                                                / HBM_PEAK_GBS, 4)}
+    if not args.no_adjoint:
+        a2 = workload("adjoint2d")
+        line["adjoint"] = dict(
+            workload="adjoint2d: 256x256 D2Q9 dendrite, FP32 forward, FP64 gradients, 2000 steps, "
+                     "checkpoint every 100",
+            **run_adjoint(a2, "fp32", 2000, 100, ["delta", "tau_pf", "D", "gbeta"]))
+        print(f"# adjoint2d: ratio {line['adjoint']['ratio']}", file=sys.stderr, flush=True)
+        e3 = workload("eutectic3d")
+        line["adjoint3d"] = dict(
+            workload="eutectic3d: 192x192x384 D3Q19, 3 phases, 2 solutes, FP32 forward, 100 steps, "
+                     "checkpoint every 25",
+            **run_adjoint(e3, "fp32", 100, 25, ["D", "D1"]))
+        print(f"# adjoint3d: ratio {line['adjoint3d']['ratio']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

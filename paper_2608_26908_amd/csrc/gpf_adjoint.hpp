@@ -5,11 +5,12 @@
 // after streaming (held on the device as the previous post-collision f*,
 // pulled on use).  One reverse step maps the adjoint of X^{n+1} to the adjoint
 // of X^n, reading X^n and X^{n+1} from the recomputed tape:
-//   k_adj_lbm   streaming transpose + collision VJP        -> lam f^n, lam phi_l', lam mu' (partial), d gbeta
-//   k_adj_w     w = chi_tot^{-1} lam mu'                   -> w, lam mu^n (direct term)
-//   k_adj_mu    faces of the mu update (gather)            -> lam mu^n, lam U^{n-1}, lam phi' (partial), lam phi^n (h^n), d D
-//   k_adj_phi1  projection + local phase-field terms        -> Rbar, lam phi^n, lam mu^n, d tau
-//   k_adj_phi2  face fluxes and cell terms (gather)         -> lam phi^n, d delta
+//   k_adj_lbm   streaming transpose + collision VJP, then   -> lam f^n, lam phi_l' (partial), d gbeta,
+//               w = chi_tot^{-1} lam mu'                        w, lam mu^n (direct term)
+//   k_adj_muphi faces of the mu update (gather), then the   -> lam mu^n, lam U^{n-1}, lam phi^n, d D,
+//               projection and local phase-field terms         Rbar, d tau
+//   k_adj_vjp   reverse of each face flux / cell term, once  -> per-role contributions, d delta
+//   k_adj_phi2  gather of those contributions               -> lam phi^n
 // Every kernel gathers into the cells it owns: no atomics, deterministic.
 // Parameter derivatives are reduced per block in FP64 and summed in a fixed
 // order.  Hessian-vector products of the gradient energy come from forward
@@ -81,8 +82,9 @@ __device__ __forceinline__ R d2h(const R (&ph)[N], int b, int a, int g) {
 template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ phi1, const R* __restrict__ mu1,
-          const R* __restrict__ lf1, const R* __restrict__ lu1, R* __restrict__ lf0,
-          R* __restrict__ t_phil, R* __restrict__ t_mu, double* __restrict__ part) {
+          const R* __restrict__ lf1, const R* __restrict__ lu1, const R* __restrict__ lmu1,
+          R* __restrict__ lf0, R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0,
+          double* __restrict__ part) {
   using L = Lat<D>;
   const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
@@ -128,7 +130,7 @@ k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ phi1, const 
     R Cl[NC], bsum = R(0);
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      Cl[i] = p.c0[N - 1][i];
+      Cl[i] = p.c0s[N - 1][i];
 #pragma unroll
       for (int k = 0; k < NC; ++k) Cl[i] += p.chi[i][k] * mu[k];
       bsum += p.gbeta[i] * (Cl[i] - p.c_ref[i]);
@@ -232,48 +234,36 @@ k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ phi1, const 
       lf0[k * p.cells + P] = v;
     }
     t_phil[P] = philb;
+    // lam mu' in full, its direct pass to lam mu^n (mu' = mu + ...) and
+    // w = chi_tot^{-T} lam mu' with chi_tot = sum_a h_a(phi') chi (symmetric)
+    R ph[N], h[N], mt[NC];
 #pragma unroll
-    for (int i = 0; i < NC; ++i) t_mu[i * p.cells + P] = mub[i];
+    for (int b = 0; b < N; ++b) ph[b] = phi1[b * p.cells + P];
+    interp_h<N, R>(ph, h);
+    R sh = R(0);
+#pragma unroll
+    for (int b = 0; b < N; ++b) sh += h[b];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      mt[i] = lmu1[i * p.cells + P] + mub[i];
+      lmu0[i * p.cells + P] = mt[i];
+    }
+    if (NC == 1) {
+      w[P] = mt[0] / (sh * p.chi[0][0]);
+    } else {
+      const R a11 = sh * p.chi[0][0], a12 = sh * p.chi[0][1];
+      const R a21 = sh * p.chi[1][0], a22 = sh * p.chi[1][NC - 1];
+      const R det = a11 * a22 - a12 * a21;
+      w[P] = (a22 * mt[0] - a21 * mt[NC - 1]) / det;
+      w[p.cells + P] = (-a12 * mt[0] + a11 * mt[NC - 1]) / det;
+    }
   }
   block_partials(gpart, part);
 }
 
 // ---------------------------------------------------------------------------
-// 2. w = chi_tot^{-T} lam mu'   (chi_tot = sum_a h_a(phi^{n+1}) chi, symmetric)
-// ---------------------------------------------------------------------------
-template <int D, int N, int NC, class R>
-__global__ void __launch_bounds__(ADJ_BLOCK)
-k_adj_w(KP<R> p, const R* __restrict__ phi1, const R* __restrict__ lmu1, const R* __restrict__ t_mu,
-        R* __restrict__ w, R* __restrict__ lmu0) {
-  const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
-  if (P >= p.cells) return;
-  R ph[N], h[N];
-#pragma unroll
-  for (int b = 0; b < N; ++b) ph[b] = phi1[b * p.cells + P];
-  interp_h<N, R>(ph, h);
-  R sh = R(0);
-#pragma unroll
-  for (int b = 0; b < N; ++b) sh += h[b];
-  R mb[NC];
-#pragma unroll
-  for (int i = 0; i < NC; ++i) {
-    mb[i] = lmu1[i * p.cells + P] + t_mu[i * p.cells + P];
-    lmu0[i * p.cells + P] = mb[i];
-  }
-  if (NC == 1) {
-    w[P] = mb[0] / (sh * p.chi[0][0]);
-  } else {
-    const R a11 = sh * p.chi[0][0], a12 = sh * p.chi[0][1];
-    const R a21 = sh * p.chi[1][0], a22 = sh * p.chi[1][NC - 1];
-    const R det = a11 * a22 - a12 * a21;
-    // transpose of the inverse
-    w[P] = (a22 * mb[0] - a21 * mb[NC - 1]) / det;
-    w[p.cells + P] = (-a12 * mb[0] + a11 * mb[NC - 1]) / det;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// 3. the mu update, gathered over the faces of each cell
+// 2-3. the mu update (gathered over the faces of each cell), then the
+// projection and local phase-field terms of the same cell
 // ---------------------------------------------------------------------------
 template <int N, int NC, class R>
 __device__ __forceinline__ void mu_quant(const KP<R>& p, const R (&ph)[N], const R (&m)[NC],
@@ -290,7 +280,7 @@ __device__ __forceinline__ void mu_quant(const KP<R>& p, const R (&ph)[N], const
   for (int b = 0; b < N; ++b)
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      R C = p.c0[b][i];
+      R C = p.c0s[b][i];
 #pragma unroll
       for (int k = 0; k < NC; ++k) C += p.chi[i][k] * m[k];
       cs[i] += h[b] * C;
@@ -300,16 +290,13 @@ __device__ __forceinline__ void mu_quant(const KP<R>& p, const R (&ph)[N], const
 }
 
 template <int D, int N, int NC, class R>
-__global__ void __launch_bounds__(ADJ_BLOCK)
-k_adj_mu(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1, const R* __restrict__ mu0,
-         const R* __restrict__ mu1, const R* __restrict__ u0, const R* __restrict__ w,
-         R* __restrict__ lmu0, R* __restrict__ lu0, R* __restrict__ t_phi1, R* __restrict__ lphi0,
-         double* __restrict__ part) {
-  const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
-  double gpart[NG] = {0, 0, 0, 0, 0, 0};
-  if (P < p.cells) {
-    int x, y, z;
-    cell_coords(P, p.sy, p.sz, p.n[0], p.n[1], x, y, z);
+__device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, int y, int z,
+                                            const R* __restrict__ phi0, const R* __restrict__ phi1,
+                                            const R* __restrict__ mu0, const R* __restrict__ mu1,
+                                            const R* __restrict__ u0, const R* __restrict__ w,
+                                            R (&mub_o)[NC], R (&Ub_o)[D], R (&p1b_o)[N], R (&p0b_o)[N],
+                                            double (&gpart)[NG]) {
+  {
     const int pos[3] = {x, y, z};
     const int64_t stride[3] = {1, p.sy, p.sz};
     R php[N], mp[NC], wp[NC], MP[NC][NC], cP[NC];
@@ -395,7 +382,7 @@ k_adj_mu(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1, const 
       R wC = R(0), cC = R(0);
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
-        R C = p.c0[b][i];
+        R C = p.c0s[b][i];
 #pragma unroll
         for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mp[k];
         wC += wp[i] * C;
@@ -446,16 +433,15 @@ k_adj_mu(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1, const 
       p0b[g] = a0;
     }
 #pragma unroll
-    for (int i = 0; i < NC; ++i) lmu0[i * p.cells + P] += mub[i];
+    for (int i = 0; i < NC; ++i) mub_o[i] = mub[i];
 #pragma unroll
-    for (int a = 0; a < D; ++a) lu0[a * p.cells + P] = Ub[a];
+    for (int a = 0; a < D; ++a) Ub_o[a] = Ub[a];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      t_phi1[b * p.cells + P] = p1b[b];
-      lphi0[b * p.cells + P] = p0b[b];
+      p1b_o[b] = p1b[b];
+      p0b_o[b] = p0b[b];
     }
   }
-  block_partials(gpart, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -463,28 +449,36 @@ k_adj_mu(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1, const 
 // ---------------------------------------------------------------------------
 template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
-k_adj_phi1(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ mu0,
-           const R* __restrict__ lphi1, const R* __restrict__ t_phil, const R* __restrict__ t_phi1,
-           R* __restrict__ lphi0, R* __restrict__ lmu0, R* __restrict__ rbar, R tshift,
-           double* __restrict__ part) {
+k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
+            const R* __restrict__ mu0, const R* __restrict__ mu1, const R* __restrict__ u0,
+            const R* __restrict__ w, const R* __restrict__ lphi1, const R* __restrict__ t_phil,
+            R* __restrict__ lphi0, R* __restrict__ lmu0, R* __restrict__ lu0, R* __restrict__ rbar,
+            uint8_t* __restrict__ rflag, R tshift, double* __restrict__ part) {
   const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
   if (P < p.cells) {
     int x, y, z;
     cell_coords(P, p.sy, p.sz, p.n[0], p.n[1], x, y, z);
+    R mubf[NC], Ubf[D], p1bf[N], p0bf[N];
+    mu_adj_cell<D, N, NC, R>(p, P, x, y, z, phi0, phi1, mu0, mu1, u0, w, mubf, Ubf, p1bf, p0bf, gpart);
+#pragma unroll
+    for (int a = 0; a < D; ++a) lu0[a * p.cells + P] = Ubf[a];
     R v[N][3][3][3];
     load_stencil<D, N, R>(p, phi0, x, y, z, v);
     const unsigned active = active_of<D, N, R>(v);
     R pb[N];
 #pragma unroll
-    for (int b = 0; b < N; ++b) pb[b] = lphi1[b * p.cells + P] + t_phi1[b * p.cells + P];
+    for (int b = 0; b < N; ++b) pb[b] = lphi1[b * p.cells + P] + p1bf[b];
     pb[N - 1] += t_phil[P];
     R p0b[N], Rb[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      p0b[b] = lphi0[b * p.cells + P];
+      p0b[b] = p0bf[b];
       Rb[b] = R(0);
     }
+    R mub[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) mub[i] = mubf[i];
     if (__builtin_popcount(active) <= 1) {
 #pragma unroll
       for (int b = 0; b < N; ++b) p0b[b] += pb[b];
@@ -513,13 +507,13 @@ k_adj_phi1(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ mu0,
         Rb[b] = p.rate * vb[b];
         taub += vb[b] * Rv[b] * (-p.rate / p.tau_pf);
       }
-      gpart[G_TAU] = (double)taub;
+      gpart[G_TAU] += (double)taub;
       // local terms: -dW/dphi / eps and -sum psi dh/dphi
       R ph[N], m[NC];
 #pragma unroll
       for (int b = 0; b < N; ++b) ph[b] = v[b][1][1][1];
 #pragma unroll
-      for (int i = 0; i < NC; ++i) m[i] = mu0[i * p.cells + P];
+      for (int i = 0; i < NC; ++i) m[i] = p.mu_ref[i] + mu0[i * p.cells + P];
 #pragma unroll
       for (int al = 0; al < N; ++al)
 #pragma unroll
@@ -548,9 +542,6 @@ k_adj_phi1(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ mu0,
         }
         ps[b] = r + p.dS[b] * tdev;
       }
-      R mub[NC];
-#pragma unroll
-      for (int i = 0; i < NC; ++i) mub[i] = R(0);
 #pragma unroll
       for (int al = 0; al < N; ++al)
 #pragma unroll
@@ -561,20 +552,23 @@ k_adj_phi1(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ mu0,
 #pragma unroll
           for (int g = 0; g < N; ++g) p0b[g] += -Rb[al] * ps[be] * d2h<N, R>(ph, be, al, g);
         }
-#pragma unroll
-      for (int i = 0; i < NC; ++i) lmu0[i * p.cells + P] += mub[i];
     }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) lmu0[i * p.cells + P] += mub[i];
+    bool nz = false;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       lphi0[b * p.cells + P] = p0b[b];
       rbar[b * p.cells + P] = Rb[b];
+      nz = nz || (Rb[b] != R(0));
     }
+    rflag[P] = nz ? 1 : 0;
   }
   block_partials(gpart, part);
 }
 
 // ---------------------------------------------------------------------------
-// 5. face fluxes and cell-centre terms of the gradient energy, gathered
+// 5. face fluxes and cell-centre terms of the gradient energy
 // ---------------------------------------------------------------------------
 
 // position along one axis of a face owner or cell-term centre: periodic axes
@@ -768,149 +762,205 @@ __device__ __forceinline__ void cell_vjp(const KP<R>& p, const R* __restrict__ p
   }
 }
 
+// 5a. Writer: every cell computes, once, the reverse of the face fluxes it
+// owns (its +e_a faces) and of its cell-centre term, and stores the
+// contributions per role: fbuf[(a NRF + r) N + b][L], cbuf[(r N + b)][P].
+// Only entries with a non-zero seed are written; fflag[a][L] / rflag[P]
+// (written by k_adj_muphi) say which.
 template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
-k_adj_phi2(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar, R* __restrict__ lphi0,
-           double* __restrict__ part) {
-  const int64_t X = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
+k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
+          const uint8_t* __restrict__ rflag, R* __restrict__ fbuf, uint8_t* __restrict__ fflag,
+          R* __restrict__ cbuf, double* __restrict__ part) {
+  constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
+  const int64_t L = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
-  if (X < p.cells) {
-    int xc[3];
-    cell_coords(X, p.sy, p.sz, p.n[0], p.n[1], xc[0], xc[1], xc[2]);
-    R acc[N];
+  if (L < p.cells) {
+    int lc[3];
+    cell_coords(L, p.sy, p.sz, p.n[0], p.n[1], lc[0], lc[1], lc[2]);
+    const int Lc[3] = {lc[0], lc[1], lc[2]};
+    R rl[N];
 #pragma unroll
-    for (int b = 0; b < N; ++b) acc[b] = R(0);
-    R ddown = R(0);
-    auto rb_at = [&](const int (&c)[3], R (&out)[N]) {
-      const int64_t j = (int64_t)c[2] * p.sz + (int64_t)c[1] * p.sy + c[0];
+    for (int b = 0; b < N; ++b) rl[b] = rbar[b * p.cells + L];
+    R dd_sum = R(0);
 #pragma unroll
-      for (int b = 0; b < N; ++b) out[b] = rbar[b * p.cells + j];
-    };
-    // ---- faces ----
-    constexpr int NR = 2 + 4 * (D - 1);
     for (int a = 0; a < D; ++a) {
-      int64_t seen[NR];
-      int nseen = 0;
-      // role offsets of a face relative to its left cell
-      int ro[NR][3];
+      int rcoord = 0;
+      bool has = owner_coord(Lc[a] + 1, p.n[a], p.per[a], rcoord);  // false: wall face
+      uint8_t flag = 0;
+      if (has) {
+        int Rc[3] = {Lc[0], Lc[1], Lc[2]};
+        Rc[a] = rcoord;
+        const int64_t Rj = (int64_t)Rc[2] * p.sz + (int64_t)Rc[1] * p.sy + Rc[0];
+        if (rflag[L] | rflag[Rj]) {
+          R Jb[N];
+          bool any = false;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) ro[r][0] = ro[r][1] = ro[r][2] = 0;
-      ro[1][a] = 1;
-      {
-        int r = 2;
+          for (int b = 0; b < N; ++b) {
+            Jb[b] = p.eps * (rl[b] - rbar[b * p.cells + Rj]) / p.dx;
+            any = any || (Jb[b] != R(0));
+          }
+          if (any) {
+            int rc[NRF][3];
+            R contrib[NRF][N], dd;
+            face_vjp<D, N, R>(p, phi0, Lc, a, Jb, rc, contrib, dd);
+            dd_sum += dd;
 #pragma unroll
-        for (int b = 0; b < D; ++b) {
-          if (b == a) continue;
-          ro[r][b] = -1;
-          ro[r + 1][b] = 1;
-          ro[r + 2][a] = 1;
-          ro[r + 2][b] = -1;
-          ro[r + 3][a] = 1;
-          ro[r + 3][b] = 1;
-          r += 4;
+            for (int r = 0; r < NRF; ++r)
+#pragma unroll
+              for (int b = 0; b < N; ++b) fbuf[((int64_t)(a * NRF + r) * N + b) * p.cells + L] = contrib[r][b];
+            flag = 1;
+          }
         }
       }
-      for (int r = 0; r < NR; ++r) {
-        int Lc[3] = {0, 0, 0}, Rc[3] = {0, 0, 0};
-        bool ok = true;
-#pragma unroll
-        for (int e = 0; e < D; ++e) ok = ok && owner_coord(xc[e] - ro[r][e], p.n[e], p.per[e], Lc[e]);
-        if (!ok) continue;
-#pragma unroll
-        for (int e = 0; e < D; ++e) Rc[e] = Lc[e];
-        if (!owner_coord(Lc[a] + 1, p.n[a], p.per[a], Rc[a])) continue;  // wall face
-        const int64_t Lj = (int64_t)Lc[2] * p.sz + (int64_t)Lc[1] * p.sy + Lc[0];
-        bool dup = false;
-        for (int i = 0; i < nseen; ++i) dup = dup || (seen[i] == Lj);
-        if (dup) continue;
-        seen[nseen++] = Lj;
-        R rl[N], rr[N], Jb[N];
-        rb_at(Lc, rl);
-        rb_at(Rc, rr);
-        bool any = false;
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-          Jb[b] = p.eps * (rl[b] - rr[b]) / p.dx;
-          any = any || (Jb[b] != R(0));
-        }
-        if (!any) continue;
-        int rc[NR][3];
-        R contrib[NR][N], dd;
-        face_vjp<D, N, R>(p, phi0, Lc, a, Jb, rc, contrib, dd);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-          bool hit = true;
-#pragma unroll
-          for (int e = 0; e < D; ++e) hit = hit && (rc[q][e] == xc[e]);
-          if (hit)
-#pragma unroll
-            for (int b = 0; b < N; ++b) acc[b] += contrib[q][b];
-        }
-        if (Lj == X) ddown += dd;
-      }
+      fflag[(int64_t)a * p.cells + L] = flag;
     }
-    // ---- cell-centre terms ----
-    {
-      constexpr int NC_R = 1 + 2 * D;
-      int64_t seen[NC_R];
-      int nseen = 0;
-      for (int r = 0; r < NC_R; ++r) {
-        int off[3] = {0, 0, 0};
-        if (r > 0) off[(r - 1) / 2] = ((r - 1) % 2) ? 1 : -1;
-        int Pc[3] = {0, 0, 0};
-        bool ok = true;
+    if (rflag[L]) {
+      R cbv[N];
 #pragma unroll
-        for (int e = 0; e < D; ++e) ok = ok && owner_coord(xc[e] - off[e], p.n[e], p.per[e], Pc[e]);
-        if (!ok) continue;
-        const int64_t Pj = (int64_t)Pc[2] * p.sz + (int64_t)Pc[1] * p.sy + Pc[0];
-        bool dup = false;
-        for (int i = 0; i < nseen; ++i) dup = dup || (seen[i] == Pj);
-        if (dup) continue;
-        seen[nseen++] = Pj;
-        R rp[N], cbv[N];
-        rb_at(Pc, rp);
-        bool any = false;
+      for (int b = 0; b < N; ++b) cbv[b] = -p.eps * rl[b];
+      int rc[NRC][3];
+      R contrib[NRC][N], dd;
+      cell_vjp<D, N, R>(p, phi0, Lc, cbv, rc, contrib, dd);
+      dd_sum += dd;
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-          cbv[b] = -p.eps * rp[b];
-          any = any || (cbv[b] != R(0));
-        }
-        if (!any) continue;
-        int rc[NC_R][3];
-        R contrib[NC_R][N], dd;
-        cell_vjp<D, N, R>(p, phi0, Pc, cbv, rc, contrib, dd);
+      for (int r = 0; r < NRC; ++r)
 #pragma unroll
-        for (int q = 0; q < NC_R; ++q) {
-          bool hit = true;
-#pragma unroll
-          for (int e = 0; e < D; ++e) hit = hit && (rc[q][e] == xc[e]);
-          if (hit)
-#pragma unroll
-            for (int b = 0; b < N; ++b) acc[b] += contrib[q][b];
-        }
-        if (Pj == X) ddown += dd;
-      }
+        for (int b = 0; b < N; ++b) cbuf[((int64_t)r * N + b) * p.cells + L] = contrib[r][b];
     }
-#pragma unroll
-    for (int b = 0; b < N; ++b) lphi0[b * p.cells + X] += acc[b];
-    gpart[G_DELTA] = (double)ddown;
+    gpart[G_DELTA] = (double)dd_sum;
   }
   block_partials(gpart, part);
 }
 
-// Sum the per-block partials of the four kernels of a reverse step in a
-// fixed order and add them to the FP64 accumulators.
+// role offsets (relative to the owner) of a face along a: 0 L, 1 R, then per
+// tangential axis b: L-e_b, L+e_b, R-e_b, R+e_b
+template <int D>
+__device__ __forceinline__ int face_role_off(int a, int r, int e) {
+  if (r == 0) return 0;
+  if (r == 1) return e == a ? 1 : 0;
+  const int t = (r - 2) / 4, k = (r - 2) % 4;  // t-th tangential axis
+  int b = 0, cnt = -1;
+  for (int q = 0; q < D; ++q)
+    if (q != a && ++cnt == t) b = q;
+  if (e == b) return (k % 2) ? 1 : -1;
+  if (e == a) return (k >= 2) ? 1 : 0;
+  return 0;
+}
+
+// 5b. Gather: lam phi^n(X) += every stored contribution whose role cell is X.
+// Cells with no flagged seed in their 3x3(x3) neighbourhood return at once.
+template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
-k_grad_accum(const double* __restrict__ part, int nparts, int nblocks, double* __restrict__ acc) {
+k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
+           const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf, R* __restrict__ lphi0) {
+  constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
+  const int64_t X = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
+  if (X >= p.cells) return;
+  int xc[3];
+  cell_coords(X, p.sy, p.sz, p.n[0], p.n[1], xc[0], xc[1], xc[2]);
+  bool any = false;
+#pragma unroll
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = nb_field(xc[0], dx, p.n[0], p.per[0]);
+        const int yy = nb_field(xc[1], dy, p.n[1], p.per[1]);
+        const int zz = (D == 3) ? nb_field(xc[2], dz, p.n[2], p.per[2]) : 0;
+        any = any || rflag[(int64_t)zz * p.sz + (int64_t)yy * p.sy + xx];
+      }
+  if (!any) return;
+  R acc[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) acc[b] = R(0);
+  // faces: owners L = X - (role offset), deduplicated (periodic axes of 1 or 2 cells alias)
+  for (int a = 0; a < D; ++a) {
+    int64_t seen[NRF];
+    int nseen = 0;
+    for (int r0 = 0; r0 < NRF; ++r0) {
+      int Lc[3] = {0, 0, 0};
+      bool ok = true;
+      for (int e = 0; e < D; ++e) ok = ok && owner_coord(xc[e] - face_role_off<D>(a, r0, e), p.n[e], p.per[e], Lc[e]);
+      if (!ok) continue;
+      const int64_t Lj = (int64_t)Lc[2] * p.sz + (int64_t)Lc[1] * p.sy + Lc[0];
+      bool dup = false;
+      for (int i = 0; i < nseen; ++i) dup = dup || (seen[i] == Lj);
+      if (dup) continue;
+      seen[nseen++] = Lj;
+      if (!fflag[(int64_t)a * p.cells + Lj]) continue;
+      for (int r = 0; r < NRF; ++r) {
+        bool hit = true;
+        for (int e = 0; e < D; ++e)
+          hit = hit && (nb_field(Lc[e], face_role_off<D>(a, r, e), p.n[e], p.per[e]) == xc[e]);
+        if (hit)
+          for (int b = 0; b < N; ++b) acc[b] += fbuf[((int64_t)(a * NRF + r) * N + b) * p.cells + Lj];
+      }
+    }
+  }
+  // cell-centre terms: centres P = X - (role offset)
+  {
+    int64_t seen[NRC];
+    int nseen = 0;
+    for (int r0 = 0; r0 < NRC; ++r0) {
+      int Pc[3] = {0, 0, 0};
+      bool ok = true;
+      for (int e = 0; e < D; ++e) {
+        const int off = (r0 > 0 && e == (r0 - 1) / 2) ? (((r0 - 1) % 2) ? 1 : -1) : 0;
+        ok = ok && owner_coord(xc[e] - off, p.n[e], p.per[e], Pc[e]);
+      }
+      if (!ok) continue;
+      const int64_t Pj = (int64_t)Pc[2] * p.sz + (int64_t)Pc[1] * p.sy + Pc[0];
+      bool dup = false;
+      for (int i = 0; i < nseen; ++i) dup = dup || (seen[i] == Pj);
+      if (dup) continue;
+      seen[nseen++] = Pj;
+      if (!rflag[Pj]) continue;
+      for (int r = 0; r < NRC; ++r) {
+        bool hit = true;
+        for (int e = 0; e < D; ++e) {
+          const int off = (r > 0 && e == (r - 1) / 2) ? (((r - 1) % 2) ? 1 : -1) : 0;
+          hit = hit && (nb_field(Pc[e], off, p.n[e], p.per[e]) == xc[e]);
+        }
+        if (hit)
+          for (int b = 0; b < N; ++b) acc[b] += cbuf[((int64_t)r * N + b) * p.cells + Pj];
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < N; ++b) lphi0[b * p.cells + X] += acc[b];
+}
+
+// Sum the per-block partials of the kernels of a reverse step in a fixed
+// order: each of GA blocks sums a contiguous slice, then one block adds the
+// GA slice sums to the FP64 accumulators.
+constexpr int GA = 256;
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_grad_slices(const double* __restrict__ part, int64_t nrows, double* __restrict__ slices) {
   __shared__ double sh[ADJ_BLOCK];
+  const int64_t per = (nrows + GA - 1) / GA;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(nrows, r0 + per);
   for (int i = 0; i < NG; ++i) {
     double s = 0.0;
-    for (int k = 0; k < nparts; ++k)
-      for (int b = threadIdx.x; b < nblocks; b += ADJ_BLOCK)
-        s += part[((int64_t)k * nblocks + b) * NG + i];
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += ADJ_BLOCK) s += part[r * NG + i];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int st = ADJ_BLOCK / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) slices[blockIdx.x * NG + i] = sh[0];
+    __syncthreads();
+  }
+}
+__global__ void __launch_bounds__(GA)
+k_grad_accum(const double* __restrict__ slices, double* __restrict__ acc) {
+  __shared__ double sh[GA];
+  for (int i = 0; i < NG; ++i) {
+    sh[threadIdx.x] = slices[threadIdx.x * NG + i];
+    __syncthreads();
+    for (int st = GA / 2; st > 0; st >>= 1) {
       if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
       __syncthreads();
     }

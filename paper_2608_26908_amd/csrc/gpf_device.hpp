@@ -65,6 +65,10 @@ template <class R> struct KP {
   R tau_pf;
   R gamma[3][3], delta[3][3];
   R chi[2][2], c0[3][2], dS[3];
+  // chemical potentials are stored as mu - mu_ref (mu_ref = far-field mu in
+  // FP32 storage, 0 in FP64), so C^a = c0s[a] + chi (mu - mu_ref)
+  R mu_ref[2], c0s[3][2];
+  double mu_ref_d[2], c0s_d[3][2];
   R D[3][2];
   R G, tdev_iso, T_E;     // T - T_E = G (x_pull - shift) if G != 0, else tdev_iso
   R tau_lb, rho0, gbeta[2], c_ref[2], grav_sign, kappa, lid_u;

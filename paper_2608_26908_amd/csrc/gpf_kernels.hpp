@@ -162,7 +162,7 @@ __device__ __forceinline__ void pf_rhs(const KP<R>& p, const R (&v)[N][3][3][3],
   // grand potentials psi^b(mu, T) = -1/2 mu.chi.mu - mu.c0[b] + dS[b] (T - T_E)
   R m[NC];
 #pragma unroll
-  for (int i = 0; i < NC; ++i) m[i] = mu[i * p.cells + P];
+  for (int i = 0; i < NC; ++i) m[i] = p.mu_ref[i] + mu[i * p.cells + P];
   const R tdev = (p.G != R(0)) ? p.G * (R(pos[p.pull_axis]) - tshift) : p.tdev_iso;
   R ps[N];
 #pragma unroll
@@ -253,7 +253,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
     for (int b = 0; b < N; ++b) {
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
-        R C = p.c0[b][i];
+        R C = p.c0s[b][i];
 #pragma unroll
         for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mun[slot][k];
         cs[i] += h[b] * C;
@@ -306,7 +306,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
     sh += h1[b];
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      R C = p.c0[b][i];
+      R C = p.c0s[b][i];
 #pragma unroll
       for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mun[0][k];
       Dl[i] -= C * (h1[b] - h0[b]);
@@ -345,7 +345,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
   R bsum = R(0);
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
-    R Cl = p.c0[N - 1][i];
+    R Cl = p.c0s[N - 1][i];
 #pragma unroll
     for (int k = 0; k < NC; ++k) Cl += p.chi[i][k] * mn[k];
     bsum += p.gbeta[i] * (Cl - p.c_ref[i]);
@@ -657,6 +657,26 @@ __global__ void k_from_double(const double* __restrict__ in, R* __restrict__ out
   if (i < n) out[i] = (R)in[i];
 }
 
+// chemical potentials: FP64 mu <-> stored mu - mu_ref, component i = idx / cells
+template <class R>
+__global__ void k_mu_to_double(const R* __restrict__ in, double* __restrict__ out, int64_t cells,
+                               int nc, double r0, double r1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc * cells) out[i] = (double)in[i] + (i < cells ? r0 : r1);
+}
+template <class R>
+__global__ void k_mu_from_double(const double* __restrict__ in, R* __restrict__ out, int64_t cells,
+                                 int nc, double r0, double r1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc * cells) out[i] = (R)(in[i] - (i < cells ? r0 : r1));
+}
+template <class R>
+__global__ void k_mu_native(const R* __restrict__ in, R* __restrict__ out, int64_t cells, int nc,
+                            R r0, R r1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc * cells) out[i] = in[i] + (i < cells ? r0 : r1);
+}
+
 // derived per-cell fields in FP64: 0 rho, 1 mixture composition C (nc comps),
 // 2 temperature, 3 active-set bitmask
 template <int D, int N, int NC, class R>
@@ -681,7 +701,7 @@ __global__ void k_derived(KP<R> p, int which, const R* __restrict__ phi, const R
     for (int i = 0; i < NC; ++i) {
       double c = 0.0;
       for (int b = 0; b < N; ++b) {
-        double C = (double)p.c0[b][i];
+        double C = p.c0s_d[b][i];
         for (int k = 0; k < NC; ++k) C += (double)p.chi[i][k] * m[k];
         c += h[b] * C;
       }
@@ -726,7 +746,7 @@ k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ m
       for (int i = 0; i < NC; ++i) {
         double c = 0.0;
         for (int b = 0; b < N; ++b) {
-          double C = (double)p.c0[b][i];
+          double C = p.c0s_d[b][i];
           for (int k = 0; k < NC; ++k) C += (double)p.chi[i][k] * m[k];
           c += h[b] * C;
         }

@@ -62,7 +62,7 @@ struct gpf_ctx {
   std::vector<StateBuf> ckpt;
   std::vector<StateBuf> tape;      // rec_every + 1 recomputed states of one segment
   StateBuf lam[2];                 // adjoint state (phi, mu, U, post-streaming f)
-  DevBuf t_phil, t_mu, t_w, t_phi1, t_rbar, t_part, t_acc;
+  DevBuf t_phil, t_w, t_rbar, t_part, t_acc, t_slices, t_rflag, t_fflag, t_fbuf, t_cbuf;
   int lam_cur = 0;                 // lam[lam_cur] holds the adjoint of the earliest state reached
   bool have_adjoint = false;
 };
@@ -152,6 +152,17 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
     }
     k.dS[a] = (R)p.dS[a];
   }
+  for (int i = 0; i < 2; ++i) {
+    k.mu_ref_d[i] = (p.precision == GPF_FP32 && i < c->nc) ? p.mu_inf[i] : 0.0;
+    k.mu_ref[i] = (R)k.mu_ref_d[i];
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < 2; ++i) {
+      double s = p.c0[a][i];
+      for (int j = 0; j < c->nc; ++j) s += p.chi[i][j] * k.mu_ref_d[j];
+      k.c0s_d[a][i] = s;
+      k.c0s[a][i] = (R)s;
+    }
   k.G = (R)p.G;
   k.tdev_iso = (R)(p.T_iso - p.T_E);
   k.T_E = (R)p.T_E;
@@ -279,8 +290,12 @@ struct Impl {
       case GPF_U: ncomp = D; break;
       default: break;
     }
-    if (ncomp) {
-      const R* src = field == GPF_PHI ? P(c->phi[s]) : field == GPF_MU ? P(c->mu[s]) : P(c->u[s]);
+    if (field == GPF_MU) {
+      const int64_t cnt = ncomp * c->cells;
+      hipLaunchKernelGGL((gpf::k_mu_to_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream,
+                         P(c->mu[s]), out, c->cells, NC, k.mu_ref_d[0], k.mu_ref_d[1]);
+    } else if (ncomp) {
+      const R* src = field == GPF_PHI ? P(c->phi[s]) : P(c->u[s]);
       const int64_t cnt = ncomp * c->cells;
       hipLaunchKernelGGL((gpf::k_to_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, src,
                          out, cnt);
@@ -320,7 +335,14 @@ struct Impl {
     const void* src = nullptr;
     switch (field) {
       case GPF_PHI: src = c->phi[s].ptr; bytes = N * c->cells * sizeof(R); break;
-      case GPF_MU: src = c->mu[s].ptr; bytes = NC * c->cells * sizeof(R); break;
+      case GPF_MU: {
+        gpf::KP<R> k = make_kp<R>(c);
+        const int64_t cnt = NC * c->cells;
+        hipLaunchKernelGGL((gpf::k_mu_native<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream,
+                           P(c->mu[s]), static_cast<R*>(dst), c->cells, NC, k.mu_ref[0], k.mu_ref[1]);
+        HIP_OR_FAIL(c, hipGetLastError());
+        return GPF_OK;
+      }
       case GPF_U: src = c->u[s].ptr; bytes = D * c->cells * sizeof(R); break;
       case GPF_F: {
         double comps = 0;
@@ -350,9 +372,13 @@ struct Impl {
     } else if (field == GPF_F) {
       hipLaunchKernelGGL((gpf::k_scatter_f<D, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0,
                          c->stream, k, in, P(c->f[s]));
+    } else if (field == GPF_MU) {
+      const int64_t cnt = NC * c->cells;
+      hipLaunchKernelGGL((gpf::k_mu_from_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, in,
+                         P(c->mu[s]), c->cells, NC, k.mu_ref_d[0], k.mu_ref_d[1]);
     } else {
-      int ncomp = field == GPF_PHI ? N : field == GPF_MU ? NC : D;
-      R* dst = field == GPF_PHI ? P(c->phi[s]) : field == GPF_MU ? P(c->mu[s]) : P(c->u[s]);
+      int ncomp = field == GPF_PHI ? N : D;
+      R* dst = field == GPF_PHI ? P(c->phi[s]) : P(c->u[s]);
       const int64_t cnt = ncomp * c->cells;
       hipLaunchKernelGGL((gpf::k_from_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, in,
                          dst, cnt);
@@ -419,20 +445,21 @@ struct Impl {
     const int64_t pstride = (int64_t)nb * gpf::NG;
     const dim3 g(nb), b(gpf::ADJ_BLOCK);
     hipLaunchKernelGGL((gpf::k_adj_lbm<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.f), P(x1.phi), P(x1.mu),
-                       P(li.f), P(li.u), P(lo.f), P(c->t_phil), P(c->t_mu), part);
-    hipLaunchKernelGGL((gpf::k_adj_w<D, N, NC, R>), g, b, 0, c->stream, k, P(x1.phi), P(li.mu), P(c->t_mu),
-                       P(c->t_w), P(lo.mu));
-    hipLaunchKernelGGL((gpf::k_adj_mu<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(x1.phi), P(x0.mu),
-                       P(x1.mu), P(x0.u), P(c->t_w), P(lo.mu), P(lo.u), P(c->t_phi1), P(lo.phi),
-                       part + pstride);
-    hipLaunchKernelGGL((gpf::k_adj_phi1<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(x0.mu), P(li.phi),
-                       P(c->t_phil), P(c->t_phi1), P(lo.phi), P(lo.mu), P(c->t_rbar),
-                       (R)tshift(c, n), part + 2 * pstride);
-    hipLaunchKernelGGL((gpf::k_adj_phi2<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(c->t_rbar),
-                       P(lo.phi), part + 3 * pstride);
-    hipLaunchKernelGGL(gpf::k_grad_accum, dim3(1), dim3(gpf::ADJ_BLOCK), 0, c->stream,
-                       static_cast<const double*>(c->t_part.ptr), 4, (int)nb,
-                       static_cast<double*>(c->t_acc.ptr));
+                       P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu), part);
+    uint8_t* rflag = static_cast<uint8_t*>(c->t_rflag.ptr);
+    uint8_t* fflag = static_cast<uint8_t*>(c->t_fflag.ptr);
+    hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(x1.phi),
+                       P(x0.mu), P(x1.mu), P(x0.u), P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
+                       P(lo.mu), P(lo.u), P(c->t_rbar), rflag, (R)tshift(c, n), part + pstride);
+    hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(c->t_rbar), rflag,
+                       P(c->t_fbuf), fflag, P(c->t_cbuf), part + 2 * pstride);
+    hipLaunchKernelGGL((gpf::k_adj_phi2<D, N, NC, R>), g, b, 0, c->stream, k, rflag, P(c->t_fbuf), fflag,
+                       P(c->t_cbuf), P(lo.phi));
+    hipLaunchKernelGGL(gpf::k_grad_slices, dim3(gpf::GA), dim3(gpf::ADJ_BLOCK), 0, c->stream,
+                       static_cast<const double*>(c->t_part.ptr), (int64_t)3 * nb,
+                       static_cast<double*>(c->t_slices.ptr));
+    hipLaunchKernelGGL(gpf::k_grad_accum, dim3(1), dim3(gpf::GA), 0, c->stream,
+                       static_cast<const double*>(c->t_slices.ptr), static_cast<double*>(c->t_acc.ptr));
   }
 
   // seed: dL/dphi at the current (final) state, FP64 host, N * cells values
@@ -447,12 +474,15 @@ struct Impl {
       for (int i = 0; i < 2 && !rc; ++i) rc = alloc_state(c, c->lam[i]);
       const unsigned nb = lin_blocks(c->cells, gpf::ADJ_BLOCK);
       if (!rc) rc = dev_alloc(c, c->t_phil, cs);
-      if (!rc) rc = dev_alloc(c, c->t_mu, NC * cs);
       if (!rc) rc = dev_alloc(c, c->t_w, NC * cs);
-      if (!rc) rc = dev_alloc(c, c->t_phi1, N * cs);
       if (!rc) rc = dev_alloc(c, c->t_rbar, N * cs);
       if (!rc) rc = dev_alloc(c, c->t_part, (size_t)4 * nb * gpf::NG * sizeof(double));
       if (!rc) rc = dev_alloc(c, c->t_acc, gpf::NG * sizeof(double));
+      if (!rc) rc = dev_alloc(c, c->t_slices, (size_t)gpf::GA * gpf::NG * sizeof(double));
+      if (!rc) rc = dev_alloc(c, c->t_rflag, (size_t)c->cells);
+      if (!rc) rc = dev_alloc(c, c->t_fflag, (size_t)D * c->cells);
+      if (!rc) rc = dev_alloc(c, c->t_fbuf, (size_t)D * (2 + 4 * (D - 1)) * N * cs);
+      if (!rc) rc = dev_alloc(c, c->t_cbuf, (size_t)(1 + 2 * D) * N * cs);
       if (rc) return rc;
     }
     while ((int64_t)c->tape.size() < K) {
@@ -721,12 +751,15 @@ void free_all(gpf_ctx* c) {
   rel(c->lam[0]);
   rel(c->lam[1]);
   dev_release(c, c->t_phil);
-  dev_release(c, c->t_mu);
   dev_release(c, c->t_w);
-  dev_release(c, c->t_phi1);
   dev_release(c, c->t_rbar);
   dev_release(c, c->t_part);
   dev_release(c, c->t_acc);
+  dev_release(c, c->t_slices);
+  dev_release(c, c->t_rflag);
+  dev_release(c, c->t_fflag);
+  dev_release(c, c->t_fbuf);
+  dev_release(c, c->t_cbuf);
 }
 
 int set_named(gpf_ctx* c, gpf_params& p, const char* name, double v) {

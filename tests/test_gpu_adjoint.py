@@ -97,3 +97,75 @@ def test_adjoint_leaves_forward_state_and_is_deterministic():
     assert np.array_equal(a, b)
     assert np.array_equal(g.read("phi"), phi)
     assert g.step_index == 12
+
+
+def _golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "adjoint2d_fd.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("precision,ref,tol", [("fp64", "grads_complex_step", 1e-8),
+                                               ("fp32", "grads", 1e-4)])
+def test_adjoint2d_full_size_against_oracle(oracle, precision, ref, tol):
+    """The 2D adjoint workload at full size (256 x 256, 2000 steps, checkpoint
+    every 100): gradients w.r.t. delta, tau, D and g beta, stored by
+    tests/golden/make_adjoint2d_fd.py from the FP64 oracle alone.  FP64: the
+    adjoint against the oracle's complex-step derivatives (exact to round-off).
+    FP32 forward with FP64 gradient accumulation: within 1e-4 relative of
+    central differences (h = 1e-6 relative) of the FP64 oracle.  (The central
+    differences themselves differ from the complex-step values by up to ~3e-5
+    in g beta, whose effect on the loss is tiny.)"""
+    from paper_2608_26908_amd.gpf import Sim
+    from paper_2608_26908_amd.workloads import workload
+    gold = _golden()
+    cfg = workload("adjoint2d")
+    steps = gold["steps"]
+    tg = gold["target_params"]
+    tcfg = dict(cfg, delta=[[0, tg["delta"]], [tg["delta"], 0]], tau_pf=tg["tau_pf"], gbeta=[tg["gbeta"]])
+    target = _target(oracle, tcfg, steps)
+    g = Sim(cfg, precision=precision)
+    g.record(cfg["checkpoint_every"])
+    g.step(steps)
+    phi = g.read("phi")
+    names = ["delta", "tau_pf", "D", "gbeta"]
+    grads = g.adjoint(phi - target, names)
+    assert 0.5 * ((phi - target) ** 2).sum() == pytest.approx(gold["loss"], rel=max(1e-6, 10 * tol))
+    for name, gv in zip(names, grads):
+        assert gv == pytest.approx(gold[ref][name], rel=tol), (name, gv, gold[ref][name])
+
+
+def test_autograd_function_and_descent(oracle):
+    """gpf_run as a torch.autograd.Function: its gradient is the adjoint's,
+    and a few descent steps on (delta, tau, g beta) lower the loss."""
+    import torch
+    from paper_2608_26908_amd.gpf import Sim, gpf_run
+    cfg = scaled("adjoint2d", [48, 48], init_radius=6.0)
+    steps, K = 120, 40
+    target = _target(oracle, cfg, steps, delta=[[0, 0.025], [0.025, 0]], tau_pf=1.2, gbeta=[2e-5])
+    tt = torch.tensor(target, device="cuda", dtype=torch.float32)
+    sim = Sim(cfg, precision="fp32")
+    init = sim.checkpoint()
+    names = ["delta", "tau_pf", "gbeta"]
+    p = torch.tensor([0.02, 1.0, 1e-5], dtype=torch.float64, requires_grad=True)
+    phi = gpf_run(p, sim, init, names, steps, K)
+    loss = 0.5 * ((phi.double() - tt.double()) ** 2).sum()
+    loss.backward()
+    ref = sim.adjoint((phi.detach().double() - tt.double()).cpu().numpy(), names)
+    assert np.allclose(p.grad.numpy(), ref, rtol=1e-12, atol=0)
+    # steepest descent in relative units: q <- q - 0.2 s (s g) / max|s g|
+    l0 = float(loss)
+    scale = torch.tensor([0.02, 1.0, 1e-5], dtype=torch.float64)
+    q, g = p.detach().clone(), p.grad.detach().clone()
+    later = []
+    for _ in range(3):
+        sg = scale * g
+        q = (q - 0.2 * scale * sg / sg.abs().max()).detach().requires_grad_(True)
+        phi = gpf_run(q, sim, init, names, steps, K)
+        loss = 0.5 * ((phi.double() - tt.double()) ** 2).sum()
+        loss.backward()
+        later.append(float(loss))
+        g = q.grad.detach().clone()
+    assert min(later) < l0, (l0, later)
