@@ -56,6 +56,26 @@ def run_gpu(cfg, precision, steps, warmup):
                 mlups=cells * steps / (ms * 1e-3) / 1e6, solute=[float(v) for v in sol])
 
 
+def copy_bandwidth(mib=1024, reps=20):
+    """Read + write GB/s of a plain device-to-device copy of `mib` MiB: the
+    bandwidth a streaming kernel can reach on this device, beside the
+    published peak."""
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        b.copy_(a)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    del a, b
+    return 2 * mib * (1 << 20) / (ms * 1e-3) / 1e9
+
+
 def run_adjoint(cfg, precision, steps, K, names):
     """Wall time of the forward run (recording checkpoints every K steps) and of
     the reverse sweep (segment recompute + adjoint kernels), same stream."""
@@ -166,6 +186,8 @@ def main():
         print(f"# fp64: {r64['mlups']:.1f} MLUPS, {r64['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
 
+    copy_gbs = copy_bandwidth()
+    print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     b32 = bytes_per_lup(cfg, 4)
     cells = r32["cells"]
     achieved = b32 * cells / (r32["k_mulbm_ms"] * 1e-3) / 1e9
@@ -193,7 +215,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_mulbm_z (chemical potential + LBM collide/stream, z-marching)",
                      "bytes_per_lup": b32,
-                     "step_frac": round(b32 * cells / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "step_frac": round(b32 * cells / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "copy_GBps": round(copy_gbs, 1)},
         "kernels_ms": {"k_phi": round(r32["k_phi_ms"], 4), "k_mulbm": round(r32["k_mulbm_ms"], 4)},
     }
     if r64:

@@ -30,22 +30,28 @@ __device__ __forceinline__ void cell_coords(const int64_t P, const int64_t sy, c
   z = (int)(P / sz);
 }
 
-// per-block FP64 partial sums of the NG parameter derivatives, fixed order
+// Per-block FP64 partial sums of the NG parameter derivatives, in a fixed
+// order (shuffle tree within each wave, then the waves in turn), added to the
+// block's running sums over the reverse sweep: every block owns its slots, so
+// no atomics are needed and the result is deterministic.
 __device__ __forceinline__ void block_partials(double (&g)[NG], double* __restrict__ part) {
-  __shared__ double sh[NG][ADJ_BLOCK];
-  const int t = threadIdx.x;
+  constexpr int NW = ADJ_BLOCK / 64;
+  __shared__ double sh[NG][NW];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 #pragma unroll
-  for (int i = 0; i < NG; ++i) sh[i][t] = g[i];
-  __syncthreads();
-  for (int s = ADJ_BLOCK / 2; s > 0; s >>= 1) {
-    if (t < s)
+  for (int i = 0; i < NG; ++i) {
+    double v = g[i];
 #pragma unroll
-      for (int i = 0; i < NG; ++i) sh[i][t] += sh[i][t + s];
-    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[i][wv] = v;
   }
-  if (t == 0)
+  __syncthreads();
+  if (t < NG) {
+    double s = sh[t][0];
 #pragma unroll
-    for (int i = 0; i < NG; ++i) part[(int64_t)blockIdx.x * NG + i] = sh[i][0];
+    for (int w = 1; w < NW; ++w) s += sh[t][w];
+    part[(int64_t)blockIdx.x * NG + t] += s;
+  }
 }
 
 // phi^n neighbourhood of a cell, walls mirrored, periodic axes wrapped
@@ -79,22 +85,26 @@ __device__ __forceinline__ R d2h(const R (&ph)[N], int b, int a, int g) {
 // ---------------------------------------------------------------------------
 // 1. streaming transpose + collision VJP
 // ---------------------------------------------------------------------------
-template <int D, int N, int NC, class R>
+// The collision depends on the pulled populations only through rho and U.
+// TAPE: rho - rho0 of the step was stored by the forward recomputation and U
+// is the step's own output, so f is not read; otherwise both are recomputed
+// from the pulled f (the last step of a checkpoint segment).
+template <int D, int N, int NC, class R, bool TAPE>
 __global__ void __launch_bounds__(ADJ_BLOCK)
-k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ phi1, const R* __restrict__ mu1,
-          const R* __restrict__ lf1, const R* __restrict__ lu1, const R* __restrict__ lmu1,
-          R* __restrict__ lf0, R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0,
-          double* __restrict__ part) {
+k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
+          const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
+          const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
+          R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
   using L = Lat<D>;
   const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
   if (P < p.cells) {
     int x, y, z;
     cell_coords(P, p.sy, p.sz, p.n[0], p.n[1], x, y, z);
-    R f[L::Q], ob[L::Q];
+    R f[TAPE ? 1 : L::Q], ob[L::Q];
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-      f[k] = pull_f<D, R>(p, fst, x, y, z, P, k);
+      if constexpr (!TAPE) f[k] = pull_f<D, R>(p, fst, x, y, z, P, k);
       // f*_k(P) streams to f_k(P + c_k), or is reflected into f_{opp k}(P)
       int dst[3] = {x + L::c(k, 0), y + L::c(k, 1), z + L::c(k, 2)};
       bool in = true;
@@ -119,12 +129,16 @@ k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ phi1, const 
     R dr = R(0), mom[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) mom[a] = R(0);
+    if constexpr (TAPE) {
+      dr = dr_t[P];
+    } else {
 #pragma unroll
-    for (int k = 0; k < L::Q; ++k) {
-      dr += f[k];
+      for (int k = 0; k < L::Q; ++k) {
+        dr += f[k];
 #pragma unroll
-      for (int a = 0; a < D; ++a)
-        if (L::c(k, a) != 0) mom[a] += R(L::c(k, a)) * f[k];
+        for (int a = 0; a < D; ++a)
+          if (L::c(k, a) != 0) mom[a] += R(L::c(k, a)) * f[k];
+      }
     }
     const R rho = p.rho0 + dr;
     R Cl[NC], bsum = R(0);
@@ -146,7 +160,10 @@ k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ phi1, const 
     R u[D], F[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      u[a] = moving ? (mom[a] + R(0.5) * FB[a]) / den : R(0);
+      if constexpr (TAPE)
+        u[a] = u1[a * p.cells + P];
+      else
+        u[a] = moving ? (mom[a] + R(0.5) * FB[a]) / den : R(0);
       F[a] = FB[a] - p.kappa * rho * sol * u[a];
     }
     R uu = R(0);
@@ -869,12 +886,56 @@ k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbu
         const int xx = nb_field(xc[0], dx, p.n[0], p.per[0]);
         const int yy = nb_field(xc[1], dy, p.n[1], p.per[1]);
         const int zz = (D == 3) ? nb_field(xc[2], dz, p.n[2], p.per[2]) : 0;
-        any = any || rflag[(int64_t)zz * p.sz + (int64_t)yy * p.sy + xx];
+        any = any | (rflag[(int64_t)zz * p.sz + (int64_t)yy * p.sy + xx] != 0);
       }
   if (!any) return;
   R acc[N];
 #pragma unroll
   for (int b = 0; b < N; ++b) acc[b] = R(0);
+  bool interior = true;
+#pragma unroll
+  for (int e = 0; e < D; ++e) interior = interior && xc[e] >= 1 && xc[e] <= p.n[e] - 2;
+  if (interior) {
+    // Away from walls and wraps every owner X - off(r) is a distinct cell and
+    // its role r is the only one landing on X: the same sums in the same
+    // order as the general path below, with every flag load issued at once.
+    uint8_t ff[D][NRF], cf[NRC];
+    int64_t Lj[D][NRF], Pj[NRC];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int r = 0; r < NRF; ++r) {
+        int64_t o = face_role_off<D>(a, r, 0) + (int64_t)face_role_off<D>(a, r, 1) * p.sy;
+        if (D == 3) o += (int64_t)face_role_off<D>(a, r, 2) * p.sz;
+        Lj[a][r] = X - o;
+        ff[a][r] = fflag[(int64_t)a * p.cells + Lj[a][r]];
+      }
+#pragma unroll
+    for (int r = 0; r < NRC; ++r) {
+      int64_t o = 0;
+      if (r > 0) {
+        const int e = (r - 1) / 2;
+        o = (((r - 1) % 2) ? 1 : -1) * (e == 0 ? (int64_t)1 : (e == 1 ? p.sy : p.sz));
+      }
+      Pj[r] = X - o;
+      cf[r] = rflag[Pj[r]];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int r = 0; r < NRF; ++r)
+        if (ff[a][r])
+#pragma unroll
+          for (int b = 0; b < N; ++b) acc[b] += fbuf[((int64_t)(a * NRF + r) * N + b) * p.cells + Lj[a][r]];
+#pragma unroll
+    for (int r = 0; r < NRC; ++r)
+      if (cf[r])
+#pragma unroll
+        for (int b = 0; b < N; ++b) acc[b] += cbuf[((int64_t)r * N + b) * p.cells + Pj[r]];
+#pragma unroll
+    for (int b = 0; b < N; ++b) lphi0[b * p.cells + X] += acc[b];
+    return;
+  }
   // faces: owners L = X - (role offset), deduplicated (periodic axes of 1 or 2 cells alias)
   for (int a = 0; a < D; ++a) {
     int64_t seen[NRF];
@@ -932,9 +993,9 @@ k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbu
   for (int b = 0; b < N; ++b) lphi0[b * p.cells + X] += acc[b];
 }
 
-// Sum the per-block partials of the kernels of a reverse step in a fixed
-// order: each of GA blocks sums a contiguous slice, then one block adds the
-// GA slice sums to the FP64 accumulators.
+// Sum the per-block running sums of the reverse sweep in a fixed order: each
+// of GA blocks sums a contiguous slice, then one block adds the GA slice sums
+// to the FP64 accumulators.
 constexpr int GA = 256;
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_grad_slices(const double* __restrict__ part, int64_t nrows, double* __restrict__ slices) {

@@ -232,7 +232,8 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
                                            const R (&mun)[2 * D + 1][NC], const R (&uc)[D],
                                            const R (&un)[D][2], const R (&ph0)[N],
                                            const R* __restrict__ fin, R* __restrict__ mu_out,
-                                           R* __restrict__ u_out, R* __restrict__ fout) {
+                                           R* __restrict__ u_out, R* __restrict__ fout,
+                                           R* __restrict__ dr_out) {
   using L = Lat<D>;
   const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
   const int pos[3] = {x, y, z};
@@ -341,6 +342,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
       if (L::c(k, a) != 0) mom[a] += R(L::c(k, a)) * f[k];
   }
   const R rho = p.rho0 + dr;
+  if (dr_out) dr_out[P] = dr;  // kept for the adjoint sweep
   const R phil = ph1[N - 1];
   R bsum = R(0);
 #pragma unroll
@@ -417,15 +419,20 @@ __device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty
 // ---------------------------------------------------------------------------
 // Phase field, z-marching: a block owns a TX x TY tile and walks along z
 // through planes [z0, z1).  phi^n of the tile plus a one-cell halo is kept in
-// a three-plane LDS ring (planes z-1, z, z+1), so every phi^n value is read
-// from memory once per block and the 9/19-point stencil reads LDS.
+// a four-slot LDS ring (planes z-1, z, z+1 in use, z+2 being filled), so every
+// phi^n value is read from memory once per block and the 9/19-point stencil
+// reads LDS.  The plane two ahead is fetched into registers before a plane is
+// computed and stored to the ring after it, so its loads are in flight during
+// the computation; one barrier per plane.
 // ---------------------------------------------------------------------------
 template <int D, int N, int NC, class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
 k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
         R tshift, int tiles_x, int tiles_y, int zc) {
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
-  __shared__ R ring[3][N][HC];
+  constexpr int NT = TX * TY, PER = (HC + NT - 1) / NT;  // halo-tile cells per thread
+  constexpr int NS = (D == 3) ? 4 : 1;
+  __shared__ R ring[NS][N][HC];
   const Tile T = tile_of(tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
@@ -433,18 +440,35 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
   const bool own = x < p.n[0] && y < p.n[1];
   const int c0 = (ly + 1) * HX + (lx + 1);
 
-  auto load = [&](int zz, int slot) {
-    const int zg = (D == 3) ? wrap_or_clamp(zz, p.n[2], p.per[2]) : 0;
-    for (int i = tid; i < HC; i += TX * TY) {
-      const int gx = wrap_or_clamp(T.x0 - 1 + i % HX, p.n[0], p.per[0]);
-      const int gy = wrap_or_clamp(T.y0 - 1 + i / HX, p.n[1], p.per[1]);
-      const int64_t j = (int64_t)zg * p.sz + (int64_t)gy * p.sy + gx;
+  // in-plane offsets of this thread's halo-tile cells (fixed along z)
+  int64_t hoff[PER];
 #pragma unroll
-      for (int q = 0; q < N; ++q) ring[slot][q][i] = phi[q * p.cells + j];
-    }
+  for (int r = 0; r < PER; ++r) {
+    const int i = min(tid + r * NT, HC - 1);
+    const int gx = wrap_or_clamp(T.x0 - 1 + i % HX, p.n[0], p.per[0]);
+    const int gy = wrap_or_clamp(T.y0 - 1 + i / HX, p.n[1], p.per[1]);
+    hoff[r] = (int64_t)gy * p.sy + gx;
+  }
+  R pre[PER][N];
+  auto fetch = [&](int zz) {
+    const int64_t zo = (D == 3) ? (int64_t)wrap_or_clamp(zz, p.n[2], p.per[2]) * p.sz : 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+      if (tid + r * NT < HC)
+#pragma unroll
+        for (int q = 0; q < N; ++q) pre[r][q] = phi[q * p.cells + zo + hoff[r]];
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+      if (tid + r * NT < HC)
+#pragma unroll
+        for (int q = 0; q < N; ++q) ring[slot][q][tid + r * NT] = pre[r][q];
   };
   auto update = [&](int z, int sm, int s0, int sp) {
     if (!own) return;
+    int xq = x, yq = y;  // opaque per plane, as in k_mulbm_z
+    asm volatile("" : "+v"(xq), "+v"(yq));
     R v[N][3][3][3];
     const int sl[3] = {sm, s0, sp};
 #pragma unroll
@@ -458,27 +482,38 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
           for (int q = 0; q < N; ++q) v[q][dz + 1][dy + 1][dx + 1] = ring[sl[dz + 1]][q][c0 + dy * HX + dx];
         }
     R res[N];
-    phi_from_stencil<D, N, NC, R>(p, v, mu, x, y, z, tshift, res);
-    const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
+    phi_from_stencil<D, N, NC, R>(p, v, mu, xq, yq, z, tshift, res);
+    const int64_t P = (int64_t)z * p.sz + (int64_t)yq * p.sy + xq;
 #pragma unroll
     for (int q = 0; q < N; ++q) phi_out[q * p.cells + P] = res[q];
   };
 
   if (D == 2) {
-    load(0, 1);
+    fetch(0);
+    store(0);
     __syncthreads();
-    update(0, 1, 1, 1);
+    update(0, 0, 0, 0);
     return;
   }
-  // ring slot of plane zz: (zz - z0 + 1) mod 3
-  load(T.z0 - 1, 0);
-  load(T.z0, 1);
+  // ring slot of plane zz: (zz - z0 + 1) mod 4
+  fetch(T.z0 - 1);
+  store(0);
+  fetch(T.z0);
+  store(1);
+  fetch(T.z0 + 1);
+  store(2);
+  fetch(T.z0 + 2);
+  __syncthreads();
   for (int z = T.z0; z < T.z1; ++z) {
     const int k = z - T.z0;
-    load(z + 1, (k + 2) % 3);
-    __syncthreads();
-    update(z, k % 3, (k + 1) % 3, (k + 2) % 3);
-    __syncthreads();
+    update(z, k & 3, (k + 1) & 3, (k + 2) & 3);
+    if (z + 1 < T.z1) {
+      // plane z+2 goes to the slot of plane z-2, which every thread finished
+      // reading before the previous barrier
+      store((k + 3) & 3);
+      if (z + 2 < T.z1) fetch(z + 3);
+      __syncthreads();
+    }
   }
 }
 
@@ -487,111 +522,166 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
 // along z: phi^{n+1}, mu^n and U_z^{n-1} of the planes z-1, z, z+1 at its own
 // column stay in registers (one new plane is loaded per step), and the
 // in-plane neighbours (x +- 1, y +- 1) of phi^{n+1}, mu^n, U_x, U_y come from
-// an LDS tile with a one-cell halo.
+// a double-buffered LDS tile: each thread writes its own column's values from
+// registers, and the threads on the tile's edge also the halo cell beyond
+// them (corners are never read).  The next plane's values are fetched into
+// registers before a plane is computed, so their loads overlap it; one
+// barrier per plane.  Threads past the grid's edge hold the wrapped (periodic)
+// or clamped (wall) column, which only serves as a neighbour.
 // ---------------------------------------------------------------------------
 template <int D, int N, int NC, class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
 k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
-          R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout, int tiles_x,
-          int tiles_y, int zc) {
+          R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout, R* __restrict__ dr_out,
+          int tiles_x, int tiles_y, int zc) {
+  static_assert(TX >= 2 && TY >= 2, "edge threads own one row and one column halo cell at most");
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
-  constexpr int NV = N + NC + 2;  // phi^{n+1}, mu^n, U_x, U_y per halo cell
-  __shared__ R sh[NV][HC];
+  constexpr int NV = N + NC + 2;  // phi^{n+1}, mu^n, U_x, U_y per tile cell
+  constexpr int NB = (D == 3) ? 2 : 1;
+  __shared__ R sh[NB][NV][HC];
   const Tile T = tile_of(tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
   const int x = T.x0 + lx, y = T.y0 + ly;
   const bool own = x < p.n[0] && y < p.n[1];
   const int c0 = (ly + 1) * HX + (lx + 1);
-  const int xo = own ? x : 0, yo = own ? y : 0;
-  const int64_t col = (int64_t)yo * p.sy + xo;
+  const int xw = wrap_or_clamp(x, p.n[0], p.per[0]), yw = wrap_or_clamp(y, p.n[1], p.per[1]);
+  const int64_t col = (int64_t)yw * p.sy + xw;
+  // halo cells: 0 the row halo (y0 - 1 or y0 + TY), 1 the column halo (x0 - 1 or x0 + TX)
+  const bool hrow = ly == 0 || ly == TY - 1, hcol = lx == 0 || lx == TX - 1;
+  const int hy = (ly == 0) ? -1 : TY, hx = (lx == 0) ? -1 : TX;
+  const int hi0 = (hy + 1) * HX + (lx + 1), hi1 = (ly + 1) * HX + (hx + 1);
+  const int64_t hoff0 = (int64_t)wrap_or_clamp(T.y0 + hy, p.n[1], p.per[1]) * p.sy + xw;
+  const int64_t hoff1 = (int64_t)yw * p.sy + wrap_or_clamp(T.x0 + hx, p.n[0], p.per[0]);
+  auto zoff = [&](int zz) -> int64_t {
+    return (D == 3) ? (int64_t)wrap_or_clamp(zz, p.n[2], p.per[2]) * p.sz : 0;
+  };
 
   // own column, planes z-1 (index 0), z (1), z+1 (2)
   R cph[3][N], cmu[3][NC], cuz[3];
-  auto load_col = [&](int zz, int i) {
-    const int zg = (D == 3) ? wrap_or_clamp(zz, p.n[2], p.per[2]) : 0;
-    const int64_t j = (int64_t)zg * p.sz + col;
+  auto fetch_col = [&](int zz, R (&ph)[N], R (&m)[NC], R& uz) {
+    const int64_t j = zoff(zz) + col;
 #pragma unroll
-    for (int q = 0; q < N; ++q) cph[i][q] = phi1[q * p.cells + j];
+    for (int q = 0; q < N; ++q) ph[q] = phi1[q * p.cells + j];
 #pragma unroll
-    for (int q = 0; q < NC; ++q) cmu[i][q] = mu[q * p.cells + j];
-    cuz[i] = (D == 3) ? uold[(D - 1) * p.cells + j] : R(0);
+    for (int q = 0; q < NC; ++q) m[q] = mu[q * p.cells + j];
+    uz = (D == 3) ? uold[(D - 1) * p.cells + j] : R(0);
   };
-  if (D == 3) {
-    load_col(T.z0 - 1, 0);
-    load_col(T.z0, 1);
-  } else {
-    load_col(0, 1);
-  }
-  for (int z = T.z0; z < T.z1; ++z) {
-    if (D == 3) load_col(z + 1, 2);
-    // in-plane tile + halo of plane z
-    for (int i = tid; i < HC; i += TX * TY) {
-      const int gx = wrap_or_clamp(T.x0 - 1 + i % HX, p.n[0], p.per[0]);
-      const int gy = wrap_or_clamp(T.y0 - 1 + i / HX, p.n[1], p.per[1]);
-      const int64_t j = (int64_t)z * p.sz + (int64_t)gy * p.sy + gx;
+  // values of one plane that go to LDS besides the column's phi and mu: own
+  // U_x, U_y and the halo cells
+  R cuxy[2], hv[2][NV], ph0[N];
+  auto fetch_plane = [&](int zz) {
+    const int64_t zo = zoff(zz);
+    cuxy[0] = uold[zo + col];
+    cuxy[1] = uold[p.cells + zo + col];
 #pragma unroll
-      for (int q = 0; q < N; ++q) sh[q][i] = phi1[q * p.cells + j];
+    for (int h = 0; h < 2; ++h) {
+      if (h == 0 ? hrow : hcol) {
+        const int64_t j = zo + (h == 0 ? hoff0 : hoff1);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) sh[N + q][i] = mu[q * p.cells + j];
-      sh[N + NC][i] = uold[j];
-      sh[N + NC + 1][i] = uold[p.cells + j];
+        for (int q = 0; q < N; ++q) hv[h][q] = phi1[q * p.cells + j];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) hv[h][N + q] = mu[q * p.cells + j];
+        hv[h][N + NC] = uold[j];
+        hv[h][N + NC + 1] = uold[p.cells + j];
+      }
     }
+  };
+  auto write_plane = [&](int bf) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) sh[bf][q][c0] = cph[1][q];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) sh[bf][N + q][c0] = cmu[1][q];
+    sh[bf][N + NC][c0] = cuxy[0];
+    sh[bf][N + NC + 1][c0] = cuxy[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (hrow) sh[bf][v][hi0] = hv[0][v];
+      if (hcol) sh[bf][v][hi1] = hv[1][v];
+    }
+  };
+  auto fetch_ph0 = [&](int zz, R (&o)[N]) {
+    const int64_t j = zoff(zz) + col;
+#pragma unroll
+    for (int q = 0; q < N; ++q) o[q] = phi0[q * p.cells + j];
+  };
+
+  if (D == 3) {
+    fetch_col(T.z0 - 1, cph[0], cmu[0], cuz[0]);
+    fetch_col(T.z0 + 1, cph[2], cmu[2], cuz[2]);
+  }
+  fetch_col(T.z0, cph[1], cmu[1], cuz[1]);
+  fetch_plane(T.z0);
+  fetch_ph0(T.z0, ph0);
+  for (int z = T.z0; z < T.z1; ++z) {
+    const int bf = (z - T.z0) & (NB - 1);
+    write_plane(bf);
     __syncthreads();
+    // next plane's loads, in flight while this plane is computed
+    R nph[N] = {}, nmu[NC] = {}, nuz = R(0), np0[N] = {};
+    if (z + 1 < T.z1) {
+      fetch_plane(z + 1);
+      fetch_ph0(z + 1, np0);
+      if (D == 3) fetch_col(z + 2, nph, nmu, nuz);
+    }
     if (own) {
-      const int64_t P = (int64_t)z * p.sz + col;
-      R ph1n[2 * D + 1][N], mun[2 * D + 1][NC], uc[D], un[D][2], ph0[N];
+      // opaque per plane: keeps the compiler from hoisting the 19 in-plane
+      // neighbour offsets out of the z loop, which would hold them in
+      // registers across it
+      int xq = x, yq = y;
+      asm volatile("" : "+v"(xq), "+v"(yq));
+      R ph1n[2 * D + 1][N], mun[2 * D + 1][NC], uc[D], un[D][2];
       const int off[4] = {-1, 1, -HX, HX};
 #pragma unroll
       for (int q = 0; q < N; ++q) {
         ph1n[0][q] = cph[1][q];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) ph1n[1 + j][q] = sh[q][c0 + off[j]];
+        for (int j = 0; j < 4; ++j) ph1n[1 + j][q] = sh[bf][q][c0 + off[j]];
         if (D == 3) {
           ph1n[2 * D - 1][q] = cph[0][q];
           ph1n[2 * D][q] = cph[2][q];
         }
-        ph0[q] = phi0[q * p.cells + P];
       }
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         mun[0][q] = cmu[1][q];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) mun[1 + j][q] = sh[N + q][c0 + off[j]];
+        for (int j = 0; j < 4; ++j) mun[1 + j][q] = sh[bf][N + q][c0 + off[j]];
         if (D == 3) {
           mun[2 * D - 1][q] = cmu[0][q];
           mun[2 * D][q] = cmu[2][q];
         }
       }
-      uc[0] = sh[N + NC][c0];
-      uc[1] = sh[N + NC + 1][c0];
-      un[0][0] = sh[N + NC][c0 - 1];
-      un[0][1] = sh[N + NC][c0 + 1];
-      un[1][0] = sh[N + NC + 1][c0 - HX];
-      un[1][1] = sh[N + NC + 1][c0 + HX];
+      uc[0] = sh[bf][N + NC][c0];
+      uc[1] = sh[bf][N + NC + 1][c0];
+      un[0][0] = sh[bf][N + NC][c0 - 1];
+      un[0][1] = sh[bf][N + NC][c0 + 1];
+      un[1][0] = sh[bf][N + NC + 1][c0 - HX];
+      un[1][1] = sh[bf][N + NC + 1][c0 + HX];
       if (D == 3) {
         uc[D - 1] = cuz[1];
         un[D - 1][0] = cuz[0];
         un[D - 1][1] = cuz[2];
       }
-      mulbm_core<D, N, NC, R>(p, x, y, z, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout);
+      mulbm_core<D, N, NC, R>(p, xq, yq, z, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout, dr_out);
     }
-    __syncthreads();
-    if (D == 3) {
 #pragma unroll
-      for (int q = 0; q < N; ++q) {
-        cph[0][q] = cph[1][q];
-        cph[1][q] = cph[2][q];
-      }
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        cmu[0][q] = cmu[1][q];
-        cmu[1][q] = cmu[2][q];
-      }
-      cuz[0] = cuz[1];
-      cuz[1] = cuz[2];
+    for (int q = 0; q < N; ++q) {
+      cph[0][q] = cph[1][q];
+      cph[1][q] = cph[2][q];
+      cph[2][q] = nph[q];
+      ph0[q] = np0[q];
     }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      cmu[0][q] = cmu[1][q];
+      cmu[1][q] = cmu[2][q];
+      cmu[2][q] = nmu[q];
+    }
+    cuz[0] = cuz[1];
+    cuz[1] = cuz[2];
+    cuz[2] = nuz;
   }
 }
 

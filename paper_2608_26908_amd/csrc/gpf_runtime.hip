@@ -33,9 +33,11 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-// one full state: phi [N], mu [nc], U [dim], stored populations f* [Q]
+// one full state: phi [N], mu [nc], U [dim], stored populations f* [Q];
+// tape states of the adjoint sweep also keep rho - rho0 of the step that
+// produced them and share two population buffers
 struct StateBuf {
-  DevBuf phi, mu, u, f;
+  DevBuf phi, mu, u, f, dr;
 };
 
 }  // namespace
@@ -60,7 +62,8 @@ struct gpf_ctx {
   // adjoint: checkpoints every rec_every steps from step rec_start
   int64_t rec_every = 0, rec_start = 0;
   std::vector<StateBuf> ckpt;
-  std::vector<StateBuf> tape;      // rec_every + 1 recomputed states of one segment
+  std::vector<StateBuf> tape;      // recomputed states of one segment (no f of their own)
+  DevBuf tape_f[2];                // populations of the recomputed states, alternating
   StateBuf lam[2];                 // adjoint state (phi, mu, U, post-streaming f)
   DevBuf t_phil, t_w, t_rbar, t_part, t_acc, t_slices, t_rflag, t_fflag, t_fbuf, t_cbuf;
   int lam_cur = 0;                 // lam[lam_cur] holds the adjoint of the earliest state reached
@@ -217,10 +220,12 @@ struct Impl {
   }
 
   struct SP {
-    R *phi, *mu, *u, *f;
+    R *phi, *mu, *u, *f, *dr;
   };
-  static SP sp(StateBuf& s) { return SP{P(s.phi), P(s.mu), P(s.u), P(s.f)}; }
-  static SP cur(gpf_ctx* c, int s) { return SP{P(c->phi[s]), P(c->mu[s]), P(c->u[s]), P(c->f[s])}; }
+  static SP sp(StateBuf& s) { return SP{P(s.phi), P(s.mu), P(s.u), P(s.f), P(s.dr)}; }
+  static SP cur(gpf_ctx* c, int s) {
+    return SP{P(c->phi[s]), P(c->mu[s]), P(c->u[s]), P(c->f[s]), nullptr};
+  }
 
   template <int TY>
   static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& in, const SP& out, R ts, int zc,
@@ -234,7 +239,7 @@ struct Impl {
                        out.phi, ts, tiles_x, tiles_y, zc);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
     hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, in.phi, out.phi,
-                       in.mu, in.u, in.f, out.mu, out.u, out.f, tiles_x, tiles_y, zc);
+                       in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y, zc);
     if (ev) (void)hipEventRecord(ev[2], c->stream);
   }
 
@@ -438,28 +443,28 @@ struct Impl {
   }
 
   // one reverse step: lam_in = adjoint of X^{n+1} -> lam_out = adjoint of X^n
-  static void reverse_step(gpf_ctx* c, const gpf::KP<R>& k, StateBuf& x0, StateBuf& x1, int64_t n,
+  static void reverse_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, int64_t n,
                            StateBuf& li, StateBuf& lo) {
     const unsigned nb = lin_blocks(c->cells, gpf::ADJ_BLOCK);
     double* part = static_cast<double*>(c->t_part.ptr);
     const int64_t pstride = (int64_t)nb * gpf::NG;
     const dim3 g(nb), b(gpf::ADJ_BLOCK);
-    hipLaunchKernelGGL((gpf::k_adj_lbm<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.f), P(x1.phi), P(x1.mu),
-                       P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu), part);
+    if (x1.dr)
+      hipLaunchKernelGGL((gpf::k_adj_lbm<D, N, NC, R, true>), g, b, 0, c->stream, k, x0.f, x1.dr, x1.u, x1.phi,
+                         x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu), part);
+    else
+      hipLaunchKernelGGL((gpf::k_adj_lbm<D, N, NC, R, false>), g, b, 0, c->stream, k, x0.f, x1.dr, x1.u,
+                         x1.phi, x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu),
+                         part);
     uint8_t* rflag = static_cast<uint8_t*>(c->t_rflag.ptr);
     uint8_t* fflag = static_cast<uint8_t*>(c->t_fflag.ptr);
-    hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(x1.phi),
-                       P(x0.mu), P(x1.mu), P(x0.u), P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
+    hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R>), g, b, 0, c->stream, k, x0.phi, x1.phi,
+                       x0.mu, x1.mu, x0.u, P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
                        P(lo.mu), P(lo.u), P(c->t_rbar), rflag, (R)tshift(c, n), part + pstride);
-    hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), g, b, 0, c->stream, k, P(x0.phi), P(c->t_rbar), rflag,
+    hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), g, b, 0, c->stream, k, x0.phi, P(c->t_rbar), rflag,
                        P(c->t_fbuf), fflag, P(c->t_cbuf), part + 2 * pstride);
     hipLaunchKernelGGL((gpf::k_adj_phi2<D, N, NC, R>), g, b, 0, c->stream, k, rflag, P(c->t_fbuf), fflag,
                        P(c->t_cbuf), P(lo.phi));
-    hipLaunchKernelGGL(gpf::k_grad_slices, dim3(gpf::GA), dim3(gpf::ADJ_BLOCK), 0, c->stream,
-                       static_cast<const double*>(c->t_part.ptr), (int64_t)3 * nb,
-                       static_cast<double*>(c->t_slices.ptr));
-    hipLaunchKernelGGL(gpf::k_grad_accum, dim3(1), dim3(gpf::GA), 0, c->stream,
-                       static_cast<const double*>(c->t_slices.ptr), static_cast<double*>(c->t_acc.ptr));
   }
 
   // seed: dL/dphi at the current (final) state, FP64 host, N * cells values
@@ -485,11 +490,17 @@ struct Impl {
       if (!rc) rc = dev_alloc(c, c->t_cbuf, (size_t)(1 + 2 * D) * N * cs);
       if (rc) return rc;
     }
-    while ((int64_t)c->tape.size() < K) {
+    while ((int64_t)c->tape.size() < K - 1) {
       StateBuf s;
-      if ((rc = alloc_state(c, s))) return rc;
+      rc = dev_alloc(c, s.phi, N * cs);
+      if (!rc) rc = dev_alloc(c, s.mu, NC * cs);
+      if (!rc) rc = dev_alloc(c, s.u, D * cs);
+      if (!rc) rc = dev_alloc(c, s.dr, cs);
+      if (rc) return rc;
       c->tape.push_back(s);
     }
+    for (int i = 0; i < 2 && K > 1; ++i)
+      if (!c->tape_f[i].ptr && (rc = dev_alloc(c, c->tape_f[i], gpf::Lat<D>::Q * cs))) return rc;
     gpf::KP<R> k = make_kp<R>(c);
     // lam^N = (seed, 0, 0, 0)
     StateBuf* li = &c->lam[0];
@@ -503,31 +514,38 @@ struct Impl {
     fill(c, li->f, gpf::Lat<D>::Q * c->cells);
     hipLaunchKernelGGL((gpf::k_fill<double>), dim3(1), dim3(gpf::NG), 0, c->stream,
                        static_cast<double*>(c->t_acc.ptr), (int64_t)gpf::NG, 0.0);
+    // per-block running sums of the parameter derivatives over the sweep
+    const int64_t nparts = (int64_t)3 * lin_blocks(c->cells, gpf::ADJ_BLOCK);
+    hipLaunchKernelGGL((gpf::k_fill<double>), dim3(lin_blocks(nparts * gpf::NG, 256)), dim3(256), 0, c->stream,
+                       static_cast<double*>(c->t_part.ptr), nparts * gpf::NG, 0.0);
     const int64_t nseg = (total + K - 1) / K;
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
       const int64_t n0 = c->rec_start + sgi * K;
       const int64_t len = std::min<int64_t>(K, total - sgi * K);
-      // recompute the segment: tape slot j holds X^{n0 + j}; slot 0 is the checkpoint
-      auto slot = [&](int64_t j) -> StateBuf& { return j == 0 ? c->ckpt[sgi] : c->tape[j - 1]; };
+      // recompute the segment: slot j holds X^{n0 + j} (slot 0 is the checkpoint)
+      // and rho - rho0 of step n0 + j - 1; its populations alternate between two buffers
+      auto slot = [&](int64_t j) -> SP {
+        if (j == 0) return sp(c->ckpt[sgi]);
+        SP s = sp(c->tape[j - 1]);
+        s.f = P(c->tape_f[j % 2]);
+        return s;
+      };
       for (int64_t j = 0; j < len - 1; ++j)
-        launch_step<4>(c, k, sp(slot(j)), sp(slot(j + 1)), (R)tshift(c, n0 + j), 8, nullptr);
-      // X^{n0 + len} is the next checkpoint or, for the last segment, the current state
-      StateBuf endst;
-      if (sgi + 1 < (int64_t)c->ckpt.size()) {
-        endst = c->ckpt[sgi + 1];
-      } else {
-        endst.phi = c->phi[c->cur];
-        endst.mu = c->mu[c->cur];
-        endst.u = c->u[c->cur];
-        endst.f = c->f[c->cur];
-      }
+        launch_step<4>(c, k, slot(j), slot(j + 1), (R)tshift(c, n0 + j), 8, nullptr);
+      // X^{n0 + len} is the next checkpoint or, for the last segment, the
+      // current state; neither holds rho, so that step reads its populations
+      const SP endst = (sgi + 1 < (int64_t)c->ckpt.size()) ? sp(c->ckpt[sgi + 1]) : cur(c, c->cur);
       for (int64_t j = len - 1; j >= 0; --j) {
-        StateBuf& x1 = (j + 1 == len) ? endst : slot(j + 1);
-        reverse_step(c, k, slot(j), x1, n0 + j, *li, *lo);
+        reverse_step(c, k, slot(j), (j + 1 == len) ? endst : slot(j + 1), n0 + j, *li, *lo);
         std::swap(li, lo);
       }
       HIP_OR_FAIL(c, hipGetLastError());
     }
+    hipLaunchKernelGGL(gpf::k_grad_slices, dim3(gpf::GA), dim3(gpf::ADJ_BLOCK), 0, c->stream,
+                       static_cast<const double*>(c->t_part.ptr), nparts, static_cast<double*>(c->t_slices.ptr));
+    hipLaunchKernelGGL(gpf::k_grad_accum, dim3(1), dim3(gpf::GA), 0, c->stream,
+                       static_cast<const double*>(c->t_slices.ptr), static_cast<double*>(c->t_acc.ptr));
+    HIP_OR_FAIL(c, hipGetLastError());
     c->lam_cur = (li == &c->lam[0]) ? 0 : 1;
     c->have_adjoint = true;
     HIP_OR_FAIL(c, hipMemcpyAsync(grads, c->t_acc.ptr, gpf::NG * sizeof(double), hipMemcpyDeviceToHost,
@@ -743,6 +761,7 @@ void free_all(gpf_ctx* c) {
     dev_release(c, s.mu);
     dev_release(c, s.u);
     dev_release(c, s.f);
+    dev_release(c, s.dr);
   };
   for (auto& s : c->ckpt) rel(s);
   for (auto& s : c->tape) rel(s);
@@ -760,6 +779,8 @@ void free_all(gpf_ctx* c) {
   dev_release(c, c->t_fflag);
   dev_release(c, c->t_fbuf);
   dev_release(c, c->t_cbuf);
+  dev_release(c, c->tape_f[0]);
+  dev_release(c, c->tape_f[1]);
 }
 
 int set_named(gpf_ctx* c, gpf_params& p, const char* name, double v) {
@@ -934,6 +955,7 @@ int gpf_record(gpf_ctx* c, int64_t checkpoint_every) {
     dev_release(c, s.mu);
     dev_release(c, s.u);
     dev_release(c, s.f);
+    dev_release(c, s.dr);
   };
   for (auto& s : c->ckpt) rel(s);
   c->ckpt.clear();

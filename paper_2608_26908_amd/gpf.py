@@ -5,8 +5,10 @@ supplies device memory (its caching allocator, through the library's
 allocation callbacks) and the stream the kernels run on.  There is no
 fallback: if libgpf.so is missing or no GPU is present, calls raise.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -135,6 +137,17 @@ def make_params(cfg, precision):
     return p
 
 
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live():
+    # contexts still open at exit give their memory back while torch's
+    # allocator is still there
+    for s in list(_LIVE):
+        s.close()
+
+
 class Sim:
     """One simulation context of the HIP library.
 
@@ -175,6 +188,7 @@ class Sim:
         if rc != GPF_OK:
             raise GPFError(rc, L.gpf_last_error(None).decode())
         self._h = h
+        _LIVE.add(self)
         self._check(L.gpf_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
     # -- plumbing ----------------------------------------------------------
