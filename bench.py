@@ -11,6 +11,7 @@ is timed beside it.  Inputs are synthetic (seed + noise from a fixed seed)
 and resident in HBM before the timed region starts.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+                    [--no-adjoint] [--no-drift]
 """
 import argparse
 import json
@@ -107,6 +108,19 @@ def run_adjoint(cfg, precision, steps, K, names):
                 grads=dict(zip(names, [float(g) for g in grads])))
 
 
+def solute_drift(cfg, precision, steps=10000):
+    """Relative change of the FP64 solute total over `steps` steps (walls and
+    periodic axes conserve it exactly in exact arithmetic)."""
+    import numpy as np
+    from paper_2608_26908_amd.gpf import Sim
+    sim = Sim(cfg, precision=precision)
+    s0 = sim.reduce("solute")
+    sim.step(steps)
+    s1 = sim.reduce("solute")
+    sim.close()
+    return float(np.max(np.abs(s1 - s0) / np.abs(s0)))
+
+
 def cpu_baseline(cfg, steps=2):
     """The FP64 oracle as it stands, on this host's cores, on a bounded
     sample of the same workload: the full grid, one untimed step, then
@@ -152,6 +166,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-drift", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a kernel of known "
                          "traffic to calibrate the HBM byte counters of a profiler run)")
@@ -239,6 +254,13 @@ def main():
                      "checkpoint every 25",
             **run_adjoint(e3, "fp32", 100, 25, ["D", "D1"]))
         print(f"# adjoint3d: ratio {line['adjoint3d']['ratio']}", file=sys.stderr, flush=True)
+    if not args.no_drift:
+        drift = {"dendrite3d_fp32": solute_drift(cfg, "fp32")}
+        e2 = workload("eutectic2d")
+        for prec in ("fp32", "fp64"):
+            drift[f"eutectic2d_{prec}"] = solute_drift(e2, prec)
+        line["solute_drift_per_1e4_steps"] = {k: float(f"{v:.3g}") for k, v in drift.items()}
+        print(f"# solute drift per 1e4 steps: {line['solute_drift_per_1e4_steps']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -178,7 +178,10 @@ int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
  *
  * gpf_record: the current state becomes checkpoint 0 of a recording; every
  * later gpf_step stores a full-state checkpoint each `checkpoint_every`
- * steps (device memory: (N + nc + dim + Q) * cells values per checkpoint).
+ * steps (device memory: (N + nc + dim + Q) * cells values per checkpoint;
+ * gpf_adjoint adds a tape of checkpoint_every - 1 states of
+ * (N + nc + dim + 1) * cells values, two population buffers and the adjoint
+ * state).
  * Errors: GPF_ERR_ARG (checkpoint_every < 1), GPF_ERR_NOMEM.
  *
  * gpf_adjoint: given dL/dphi at the current state (FP64 host array of

@@ -341,8 +341,9 @@ __device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, in
 #pragma unroll
       for (int si = 0; si < 2; ++si) {
         const int s = si ? 1 : -1;
+        // wall faces carry no flux: their seed is zeroed below rather than
+        // branched around, so the loads of all faces can be issued together
         const bool wall = !p.per[a] && ((s < 0 && pos[a] == 0) || (s > 0 && pos[a] == p.n[a] - 1));
-        if (wall) continue;
         const int q = nb_field(pos[a], s, p.n[a], p.per[a]);
         const int64_t Qj = P + (int64_t)(q - pos[a]) * stride[a];
         R phq[N], mq[NC], wq[NC], MQ[NC][NC], cQ[NC];
@@ -360,7 +361,7 @@ __device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, in
         R Jb[NC], dmu[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
-          Jb[i] = dtdx * sgn * (wq[i] - wp[i]);
+          Jb[i] = wall ? R(0) : dtdx * sgn * (wq[i] - wp[i]);
           dmu[i] = sgn * (mq[i] - mp[i]);  // mu_R - mu_L
         }
 #pragma unroll
@@ -866,7 +867,7 @@ __device__ __forceinline__ int face_role_off(int a, int r, int e) {
 }
 
 // 5b. Gather: lam phi^n(X) += every stored contribution whose role cell is X.
-// Cells with no flagged seed in their 3x3(x3) neighbourhood return at once.
+// Cells with no flagged seed in their 9/19-point neighbourhood return at once.
 template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
@@ -876,6 +877,8 @@ k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbu
   if (X >= p.cells) return;
   int xc[3];
   cell_coords(X, p.sy, p.sz, p.n[0], p.n[1], xc[0], xc[1], xc[2]);
+  // every role offset, and every face's other cell, lies in the 9/19-point
+  // neighbourhood (at most two non-zero components), so the 3D corners are skipped
   bool any = false;
 #pragma unroll
   for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
@@ -883,6 +886,7 @@ k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbu
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
+        if (dx != 0 && dy != 0 && dz != 0) continue;
         const int xx = nb_field(xc[0], dx, p.n[0], p.per[0]);
         const int yy = nb_field(xc[1], dy, p.n[1], p.per[1]);
         const int zz = (D == 3) ? nb_field(xc[2], dz, p.n[2], p.per[2]) : 0;

@@ -204,6 +204,20 @@ struct Ops {
 
 inline unsigned lin_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// z-marching launch shape: 64 x GPF_TILE_Y tiles; each block of k_phi_z walks
+// GPF_ZCHUNK_PHI planes, each of k_mulbm_z GPF_ZCHUNK_MU (best measured of
+// 64 x {2, 4, 8} x {4, 8, 16, 32} on the 256^3 dendrite)
+#ifndef GPF_TILE_Y
+#define GPF_TILE_Y 4
+#endif
+#ifndef GPF_ZCHUNK_PHI
+#define GPF_ZCHUNK_PHI 16
+#endif
+#ifndef GPF_ZCHUNK_MU
+#define GPF_ZCHUNK_MU 4
+#endif
+constexpr int kTileY = GPF_TILE_Y, kZChunkPhi = GPF_ZCHUNK_PHI, kZChunkMu = GPF_ZCHUNK_MU;
+
 template <int D, int N, int NC, class R>
 struct Impl {
   static R* P(DevBuf& b) { return static_cast<R*>(b.ptr); }
@@ -227,26 +241,26 @@ struct Impl {
     return SP{P(c->phi[s]), P(c->mu[s]), P(c->u[s]), P(c->f[s]), nullptr};
   }
 
-  template <int TY>
-  static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& in, const SP& out, R ts, int zc,
+  static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& in, const SP& out, R ts,
                           hipEvent_t* ev) {
-    constexpr int TX = 64;
+    constexpr int TX = 64, TY = kTileY;
     const int tiles_x = (int)((c->n[0] + TX - 1) / TX), tiles_y = (int)((c->n[1] + TY - 1) / TY);
-    const int tiles_z = (D == 3) ? (int)((c->n[2] + zc - 1) / zc) : 1;
-    const dim3 grid((unsigned)tiles_x * (unsigned)tiles_y * (unsigned)tiles_z), block(TX * TY);
+    auto grid = [&](int zc) {
+      const int tiles_z = (D == 3) ? (int)((c->n[2] + zc - 1) / zc) : 1;
+      return dim3((unsigned)tiles_x * (unsigned)tiles_y * (unsigned)tiles_z);
+    };
+    const dim3 block(TX * TY);
     if (ev) (void)hipEventRecord(ev[0], c->stream);
-    hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, in.phi, in.mu,
-                       out.phi, ts, tiles_x, tiles_y, zc);
+    hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid(kZChunkPhi), block, 0, c->stream, k, in.phi,
+                       in.mu, out.phi, ts, tiles_x, tiles_y, kZChunkPhi);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
-    hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY>), grid, block, 0, c->stream, k, in.phi, out.phi,
-                       in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y, zc);
+    hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY>), grid(kZChunkMu), block, 0, c->stream, k, in.phi,
+                       out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y, kZChunkMu);
     if (ev) (void)hipEventRecord(ev[2], c->stream);
   }
 
   static int step(gpf_ctx* c, int64_t nsteps, double* kernel_ms, int nk) {
     gpf::KP<R> k = make_kp<R>(c);
-    // tile 64 x 4, 8 planes per block (measured best of 64 x {4, 8} x {8..64} on 256^3)
-    constexpr int kZChunk = 8;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (kernel_ms) {
       for (int i = 0; i < 3; ++i) HIP_OR_FAIL(c, hipEventCreate(&ev[i]));
@@ -256,7 +270,7 @@ struct Impl {
     for (int64_t it = 0; it < nsteps; ++it) {
       const int s = c->cur, t = 1 - c->cur;
       const R ts = (R)tshift(c, c->step);
-      launch_step<4>(c, k, cur(c, s), cur(c, t), ts, kZChunk, kernel_ms ? ev : nullptr);
+      launch_step(c, k, cur(c, s), cur(c, t), ts, kernel_ms ? ev : nullptr);
       HIP_OR_FAIL(c, hipGetLastError());
       if (kernel_ms) {
         HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
@@ -531,7 +545,7 @@ struct Impl {
         return s;
       };
       for (int64_t j = 0; j < len - 1; ++j)
-        launch_step<4>(c, k, slot(j), slot(j + 1), (R)tshift(c, n0 + j), 8, nullptr);
+        launch_step(c, k, slot(j), slot(j + 1), (R)tshift(c, n0 + j), nullptr);
       // X^{n0 + len} is the next checkpoint or, for the last segment, the
       // current state; neither holds rho, so that step reads its populations
       const SP endst = (sgi + 1 < (int64_t)c->ckpt.size()) ? sp(c->ckpt[sgi + 1]) : cur(c, c->cur);

@@ -135,6 +135,8 @@ def test_fp32_within_tolerance_after_100_steps(oracle, name, n):
     dphi = np.abs(g.read("phi") - o.get("phi")).max()
     ug, uo = g.read("u"), o.get("u")
     rl2 = np.sqrt(((ug - uo) ** 2).sum() / (uo ** 2).sum())
+    print(f"FP32 vs FP64 oracle, {name} {cfg['n'][:cfg['dim']]}, 100 steps: "
+          f"max|dphi| {dphi:.2e}, rel-L2(U) {rl2:.2e}")
     assert dphi <= 1e-5, dphi
     assert rl2 <= 1e-4, rl2
     assert rel_err(g.read("mu"), o.get("mu")) <= 1e-5
