@@ -92,7 +92,7 @@ struct Par {
   int dim, N, nc, potential, periodic[3], pull_axis, grav_axis, grav_sign;
   long n[3];
   S dx, dt, eps, tau_pf, gamma[3][3], delta[3][3], chi[2][2], c0[3][2], dS[3], T_E, T_iso,
-      D[3][2], G, V, y0, tau_lb, rho0, gbeta[2], c_ref[2], h_drag, W0, lid_u;
+      D[3][2], G, V, y0, tau_lb, rho0, gbeta[2], c_ref[2], h_drag, W0, lid_u, eta[3];
 };
 
 template <class S>
@@ -141,6 +141,7 @@ Par<S> lift(const gpfo_params& p) {
   q.h_drag = p.h_drag;
   q.W0 = p.W0;
   q.lid_u = p.lid_u;
+  for (int a = 0; a < 3; ++a) q.eta[a] = p.eta[a];
   return q;
 }
 
@@ -566,16 +567,46 @@ void mu_cell(const Grid& g, const Par<S>& p, const State<S>& st, const std::vect
 }
 
 /* ---------------- S5: forces, moments, BGK collision ------------------------ */
+/* Shrinkage force (Eq. shrinkage): G_S = sum_a eta_a (dphi_a/dt) n_a with
+ * eta_a = (rho_a - rho_liq)/rho_liq and n_a = grad phi_a / |grad phi_a|.
+ * Reading: dphi/dt over one lattice time step (one LBM step per PF step), so
+ * dphi_a/dt = phi^{n+1}_a - phi^n_a in lattice units; the normal from central
+ * differences of phi^{n+1} (walls mirrored, periodic axes wrapped); n_a = 0
+ * where |grad phi_a|^2 <= 1e-24. */
+template <class S>
+void shrinkage_force(const Grid& g, const Par<S>& p, const std::vector<S>& phi_old,
+                     const std::vector<S>& phi_new, const long* x, S* GS) {
+  const long cells = g.cells();
+  const long P = g.idx(x[0], x[1], x[2]);
+  for (int a = 0; a < 3; ++a) GS[a] = S(0.0);
+  for (int b = 0; b < p.N; ++b) {
+    if (p.eta[b] == S(0.0)) continue;
+    S grad[3] = {0, 0, 0}, gg = 0;
+    for (int a = 0; a < p.dim; ++a) {
+      int op[3] = {0, 0, 0}, om[3] = {0, 0, 0};
+      op[a] = 1;
+      om[a] = -1;
+      grad[a] = (phi_new[b * cells + g.field_nb(x, op)] - phi_new[b * cells + g.field_nb(x, om)]) /
+                (S(2.0) * p.dx);
+      gg += grad[a] * grad[a];
+    }
+    if (re(gg) <= 1e-24) continue;
+    S rate = p.eta[b] * (phi_new[b * cells + P] - phi_old[b * cells + P]) / std::sqrt(gg);
+    for (int a = 0; a < p.dim; ++a) GS[a] += rate * grad[a];
+  }
+}
+
 /* rho = sum f, m = sum f c (Eq. rhovel);
  * buoyancy F_B = -rho phi_l sum_i gbeta_i (C^l_i(mu^{n+1}) - C_ref_i) g_hat (Eq. buoyancy,
  *   g_hat the unit gravity vector, gbeta the signed product g beta_i);
+ * shrinkage G_S as above; explicit force F_E = F_B + G_S;
  * drag G_D = -kappa rho (1 - phi_l)^2 U, kappa = 2 nu h / W0, nu = (tau - 1/2)/3;
  * velocity with Guo's half-force correction, the drag taken implicitly:
- *   U = (m + F_B/2) / (rho (1 + kappa (1 - phi_l)^2 / 2)),  U = 0 where phi_l = 0;
- * F = F_B + G_D;  f* = f - (f - f^eq)/tau + Guo source. */
+ *   U = (m + F_E/2) / (rho (1 + kappa (1 - phi_l)^2 / 2)),  U = 0 where phi_l = 0;
+ * F = F_E + G_D;  f* = f - (f - f^eq)/tau + Guo source. */
 template <class S>
 void collide_cell(const Lattice& L, const Par<S>& p, const S* fin, S phil,
-                  const S* mu_new, S* fout, S* u_out) {
+                  const S* mu_new, const S* GS, S* fout, S* u_out) {
   const int d = p.dim;
   S rho = 0, m[3] = {0, 0, 0};
   for (int k = 0; k < L.Q; ++k) {
@@ -588,6 +619,7 @@ void collide_cell(const Lattice& L, const Par<S>& p, const S* fin, S phil,
   for (int i = 0; i < p.nc; ++i) b += p.gbeta[i] * (Cl[i] - p.c_ref[i]);
   S FB[3] = {0, 0, 0};
   FB[p.grav_axis] = -rho * phil * b * S((double)p.grav_sign);
+  for (int a = 0; a < d; ++a) FB[a] += GS[a];
   S nu = (p.tau_lb - S(0.5)) / S(3.0);
   S kappa = S(2.0) * nu * p.h_drag / p.W0;
   S sol = (S(1.0) - phil) * (S(1.0) - phil);
@@ -654,10 +686,13 @@ void step_once(const Grid& g, const Lattice& L, const Par<S>& p, State<S>& st) {
   /* S5: collision at every cell with phi^{n+1}_l and mu^{n+1} */
 #pragma omp parallel for schedule(static)
   for (long P = 0; P < cells; ++P) {
-    S fin[19], fo[19], uo[3], mnew[2];
+    S fin[19], fo[19], uo[3], mnew[2], GS[3];
+    long x[3];
+    g.coords(P, x);
+    shrinkage_force(g, p, st.phi, phin, x, GS);
     for (int k = 0; k < Q; ++k) fin[k] = st.f[k * cells + P];
     for (int i = 0; i < nc; ++i) mnew[i] = mun[i * cells + P];
-    collide_cell(L, p, fin, phin[(N - 1) * cells + P], mnew, fo, uo);
+    collide_cell(L, p, fin, phin[(N - 1) * cells + P], mnew, GS, fo, uo);
     for (int k = 0; k < Q; ++k) fpost[k * cells + P] = fo[k];
     for (int a = 0; a < d; ++a) un[a * cells + P] = uo[a];
   }

@@ -15,7 +15,8 @@
  *     by the paper (Sec. 2.1) and U = 0 in solids;
  *   - BGK lattice-Boltzmann collide + stream, Eqs. (LBMEq_1), (f^eq),
  *     (discreteForce), with the drag force G_D and solutal buoyancy G_B
- *     (Eq. buoyancy), moments Eq. (rhovel); D2Q9 from Table LBM_Schemes,
+ *     (Eq. buoyancy) and the shrinkage force G_S (Eq. shrinkage), moments
+ *     Eq. (rhovel); D2Q9 from Table LBM_Schemes,
  *     D3Q19 (textbook set; the paper's own 3D lattice is D3Q27);
  *   - staggered order of Algorithm phfLBM (App. A): phi -> mu -> LBM.
  * Every reading of a silent or garbled passage is listed in the design doc and
@@ -68,6 +69,7 @@ typedef struct {
   double init_center[3], init_radius;
   double lam_width, lam_height;
   double mu_inf[2], noise_sigma;
+  double eta[3];          /* shrinkage: eta_a = (rho_a - rho_liq) / rho_liq (0: off) */
 } gpfo_params;
 
 typedef struct gpfo_sim gpfo_sim;

@@ -46,7 +46,7 @@ class _Params(ctypes.Structure):
         ("init_kind", ctypes.c_int32), ("init_center", ctypes.c_double * 3),
         ("init_radius", ctypes.c_double), ("lam_width", ctypes.c_double),
         ("lam_height", ctypes.c_double), ("mu_inf", ctypes.c_double * 2),
-        ("noise_sigma", ctypes.c_double),
+        ("noise_sigma", ctypes.c_double), ("eta", ctypes.c_double * 3),
     ]
 
 
@@ -144,6 +144,7 @@ def make_params(cfg):
     _fill(p.c_ref, cfg["c_ref"], (2,))
     _fill(p.init_center, cfg.get("init_center", [0, 0, 0]), (3,))
     _fill(p.mu_inf, cfg["mu_inf"], (2,))
+    _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]), (3,))
     return p
 
 

@@ -26,6 +26,7 @@ _COMMON = dict(
     G=0.0, V=0.0, y0=0.0, rho0=1.0, h_drag=2.757, W0=4.0, lid_u=0.0,
     noise_sigma=1e-3, seed=1, lam_width=0.0, lam_height=0.0,
     init_center=[0.0, 0.0, 0.0], init_radius=0.0,
+    eta=[0.0, 0.0, 0.0],  # shrinkage (rho_a - rho_liq) / rho_liq per phase; the paper's 1.2 / 1.0 gives 0.2
 )
 
 WORKLOADS = {

@@ -290,6 +290,17 @@ class Step:
             b = sum(cf["gbeta"][i] * (Cl[i] - cf["c_ref"][i]) for i in range(self.nc))
             FB = [0.0] * d
             FB[cf["grav_axis"]] = -rho * phil * b * cf["grav_sign"]
+            # shrinkage: eta_b times the change of phi_b over the step along the
+            # unit normal of phi^{n+1}_b (central differences)
+            for bb, eta in enumerate(cf.get("eta", [0.0] * 3)[:N]):
+                if eta == 0.0:
+                    continue
+                g = [self.gradc(dict(phi=phin), bb, x, e) for e in range(d)]
+                gg = sum(v * v for v in g)
+                if gg > 1e-24:
+                    dphi = phin[(bb,) + tuple(reversed(x))] - st["phi"][(bb,) + tuple(reversed(x))]
+                    for a in range(d):
+                        FB[a] += eta * dphi * g[a] / gg ** 0.5
             nu = (tau - 0.5) / 3
             kap = 2 * nu * cf["h_drag"] / cf["W0"] * (1 - phil) ** 2
             if phil == 0:

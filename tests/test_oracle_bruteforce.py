@@ -39,3 +39,13 @@ def test_ten_steps_vs_literal_evaluator(oracle, kind):
 def test_lid_and_well_vs_literal_evaluator(oracle):
     cfg = busy_config("binary2d", [8, 8], periodic=[0, 0], lid_u=0.05, potential="well")
     _compare(oracle, cfg, random_state(cfg, 13), 3)
+
+
+@pytest.mark.parametrize("kind", ["binary2d", "ternary2d", "binary3d"])
+def test_shrinkage_vs_literal_evaluator(oracle, kind):
+    """The shrinkage force (Eq. shrinkage) switched on with the paper's
+    density ratio rho_s / rho_l = 1.2 (eta = 0.2 for every solid)."""
+    n = [8, 8] if "2d" in kind else [4, 4, 4]
+    cfg = busy_config(kind, n)
+    cfg["eta"] = [0.2, 0.2, 0.0] if cfg["N"] == 3 else [0.2, 0.0, 0.0]
+    _compare(oracle, cfg, random_state(cfg, 14), 3)

@@ -387,3 +387,50 @@ def test_lid_driven_cavity_self_convergence(oracle):
     # the top and returns below
     centre = c[0, :, 3:5].mean(1)
     assert centre[-1] > 0.3 and centre.min() < -0.1
+
+
+def test_shrinkage_drives_flow_toward_the_growing_solid(oracle):
+    """Eq. (shrinkage) with a denser solid (eta > 0) draws liquid toward a
+    growing seed, and a lighter one pushes it away (the paper's observation
+    of flow directed at the growing tip).  Buoyancy off, no noise: the mean
+    radial velocity of the liquid around the seed, averaged over 200 steps
+    (the closed box rings acoustically), has the sign of -eta, nearly
+    antisymmetric in eta; with eta = 0 the fluid stays at rest exactly."""
+    from paper_2608_26908_amd.workloads import scaled
+    yy, xx = np.mgrid[0:64, 0:64]
+    c = 31.5
+    r = np.hypot(xx - c, yy - c)
+    mean_ur = {}
+    for eta in (0.2, -0.2, 0.0):
+        cfg = scaled("dendrite2d", [64, 64], gbeta=[0.0], eta=[eta, 0.0, 0.0], noise_sigma=0.0)
+        s = oracle.OracleSim(cfg)
+        acc = []
+        for _ in range(100):
+            s.step(2)
+            u, phil = s.get("u"), s.get("phi")[1]
+            liquid = (phil > 0.999) & (r < 20)
+            ur = (u[0] * (xx - c) + u[1] * (yy - c)) / np.maximum(r, 1e-9)
+            acc.append(ur[liquid].mean())
+        mean_ur[eta] = float(np.mean(acc))
+        if eta == 0.0:
+            assert np.abs(s.get("u")).max() == 0.0
+    assert mean_ur[0.2] < 0 < mean_ur[-0.2], mean_ur
+    assert abs(mean_ur[0.2] + mean_ur[-0.2]) <= 0.05 * abs(mean_ur[0.2]), mean_ur
+
+
+def test_shrinkage_response_is_linear_in_eta(oracle):
+    """G_S enters the first step's velocity only through the half-force term
+    of Guo's velocity, so the change of U is exactly linear in eta."""
+    from inputs import busy_config, random_state
+    cfg = busy_config("binary2d", [12, 10], gbeta=[0.0])
+    st = random_state(cfg, 15)
+    out = {}
+    for eta in (0.0, 0.1, 0.3):
+        s = oracle.OracleSim(dict(cfg, eta=[eta, 0.0, 0.0]))
+        for k in ("phi", "mu", "f", "u"):
+            s.set(k, st[k])
+        s.step(1)
+        out[eta] = s.get("u")
+    d1, d3 = out[0.1] - out[0.0], out[0.3] - out[0.0]
+    assert np.abs(d1).max() > 1e-4
+    assert np.abs(d3 - 3 * d1).max() <= 1e-12 * np.abs(d3).max()
