@@ -201,6 +201,12 @@ def main():
         print(f"# fp64: {r64['mlups']:.1f} MLUPS, {r64['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
 
+    # the shrinkage force of Eq. (shrinkage) on (rho_s / rho_l = 1.2): the same
+    # workload, extra arithmetic on values the kernel already holds
+    rs = run_gpu(workload(args.workload, eta=[0.2, 0.0, 0.0]), "fp32", min(args.steps, 100),
+                 args.warmup)
+    print(f"# fp32 with shrinkage: {rs['mlups']:.1f} MLUPS, {rs['ms_per_step']:.3f} ms/step",
+          file=sys.stderr, flush=True)
     copy_gbs = copy_bandwidth()
     print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     b32 = bytes_per_lup(cfg, 4)
@@ -234,6 +240,9 @@ def main():
                      "copy_GBps": round(copy_gbs, 1)},
         "kernels_ms": {"k_phi": round(r32["k_phi_ms"], 4), "k_mulbm": round(r32["k_mulbm_ms"], 4)},
     }
+    line["shrinkage"] = {"value": round(rs["mlups"], 2), "unit": "MLUPS", "eta": [0.2, 0.0, 0.0],
+                         "ms_per_step": round(rs["ms_per_step"], 4),
+                         "k_phi_ms": round(rs["k_phi_ms"], 4), "k_mulbm_ms": round(rs["k_mulbm_ms"], 4)}
     if r64:
         b64 = bytes_per_lup(cfg, 8)
         line["fp64"] = {"value": round(r64["mlups"], 2), "unit": "MLUPS",

@@ -106,6 +106,10 @@ typedef struct {
   double c_ref[2];        /* reference liquid composition of Eq. (buoyancy) */
   int32_t grav_axis, grav_sign; /* unit gravity vector = grav_sign * e_{grav_axis} */
   double h_drag, W0;      /* drag kappa = 2 nu h / W0 of G_D, nu = (tau_lb - 1/2)/3 */
+  double eta[3];          /* shrinkage force G_S of Eq. (shrinkage): eta_a = (rho_a - rho_liq) / rho_liq
+                             per phase (liquid 0); G_S = sum_a eta_a (phi^{n+1}_a - phi^n_a) n_a per
+                             lattice step, n_a the unit normal of phi^{n+1}_a from central differences.
+                             All 0: off.  gpf_adjoint refuses a context with G_S on. */
   double lid_u;           /* test only: upper wall of axis 1 moves along axis 0 (cavity) */
   int32_t init_kind;      /* gpf_init_kind */
   double init_center[3], init_radius; /* seed centre (cell units, cell i at coordinate i), radius */
@@ -196,7 +200,7 @@ int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
  * accumulated in FP64 in a fixed order; the adjoint fields have the
  * context's precision.  Synchronises.  Errors: GPF_ERR_STATE (nothing
  * recorded), GPF_ERR_ARG (count, unknown name, more than 6 names),
- * GPF_ERR_NOMEM.
+ * GPF_ERR_UNSUPPORTED (shrinkage force on: eta != 0), GPF_ERR_NOMEM.
  *
  * gpf_adjoint_state: after gpf_adjoint, dL/d(initial recorded state) for
  * GPF_PHI, GPF_MU, GPF_U (velocity of the step before) or GPF_F (the

@@ -72,6 +72,8 @@ template <class R> struct KP {
   R D[3][2];
   R G, tdev_iso, T_E;     // T - T_E = G (x_pull - shift) if G != 0, else tdev_iso
   R tau_lb, rho0, gbeta[2], c_ref[2], grav_sign, kappa, lid_u;
+  R eta[3];               // shrinkage (rho_a - rho_liq) / rho_liq per phase
+  int shrink;             // some eta != 0
   R qmin2;                // |q|^2 below which the anisotropy direction is undefined
   R w[19];                // lattice weights in R
 };
@@ -79,6 +81,9 @@ template <class R> struct KP {
 // ---------------------------------------------------------------------------
 // Pointwise model functions.
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float gsqrt(float v) { return sqrtf(v); }
+__device__ __forceinline__ double gsqrt(double v) { return sqrt(v); }
 
 // Forward-mode dual number: value and one directional derivative.  Used to
 // differentiate dA/dq (Hessian-vector products and the derivative in delta)

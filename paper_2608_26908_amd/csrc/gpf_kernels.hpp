@@ -226,7 +226,9 @@ __device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N]
 //   a-component of U^{n-1} at those neighbours; ph0: phi^n at the cell.
 // The populations are pulled from fin (the previous post-collision f*).
 // ---------------------------------------------------------------------------
-template <int D, int N, int NC, class R>
+// SH: the shrinkage force is on (a separate instance keeps the registers of
+// the common case unchanged)
+template <int D, int N, int NC, class R, bool SH>
 __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
                                            const R (&ph1n)[2 * D + 1][N],
                                            const R (&mun)[2 * D + 1][NC], const R (&uc)[D],
@@ -356,6 +358,26 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
 #pragma unroll
   for (int a = 0; a < D; ++a) FB[a] = R(0);
   FB[p.grav_axis] = -rho * phil * bsum * p.grav_sign;
+  if constexpr (SH) {
+    // shrinkage, Eq. (shrinkage): eta_b (phi^{n+1}_b - phi^n_b) along the unit
+    // normal of phi^{n+1}_b (central differences over the 7-point values held
+    // for the mu update; walls mirrored), per lattice step
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      if (p.eta[b] == R(0)) continue;
+      R g[D], gg = R(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        g[a] = (ph1n[2 + 2 * a][b] - ph1n[1 + 2 * a][b]) / (R(2) * p.dx);
+        gg += g[a] * g[a];
+      }
+      if (gg > p.qmin2) {
+        const R s = p.eta[b] * (ph1n[0][b] - ph0[b]) / gsqrt(gg);
+#pragma unroll
+        for (int a = 0; a < D; ++a) FB[a] += s * g[a];
+      }
+    }
+  }
   const R sol = (R(1) - phil) * (R(1) - phil);
   R u[D], F[D];
 #pragma unroll
@@ -529,7 +551,7 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
 // barrier per plane.  Threads past the grid's edge hold the wrapped (periodic)
 // or clamped (wall) column, which only serves as a neighbour.
 // ---------------------------------------------------------------------------
-template <int D, int N, int NC, class R, int TX, int TY>
+template <int D, int N, int NC, class R, int TX, int TY, bool SH>
 __global__ void __launch_bounds__(TX * TY)
 k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
@@ -664,7 +686,7 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
         un[D - 1][0] = cuz[0];
         un[D - 1][1] = cuz[2];
       }
-      mulbm_core<D, N, NC, R>(p, xq, yq, z, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout, dr_out);
+      mulbm_core<D, N, NC, R, SH>(p, xq, yq, z, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout, dr_out);
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {

@@ -179,6 +179,11 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
   const double nu = (p.tau_lb - 0.5) / 3.0;
   k.kappa = (R)(2.0 * nu * p.h_drag / p.W0);
   k.lid_u = (R)p.lid_u;
+  k.shrink = 0;
+  for (int a = 0; a < 3; ++a) {
+    k.eta[a] = (a < c->N) ? (R)p.eta[a] : R(0);
+    if (k.eta[a] != R(0)) k.shrink = 1;
+  }
   k.qmin2 = (sizeof(R) == 8) ? (R)1e-24 : (R)1e-12;
   for (int q = 0; q < c->Q; ++q)
     k.w[q] = (R)((c->dim == 2) ? gpf::Lat<2>::w(q) : gpf::Lat<3>::w(q));
@@ -254,8 +259,14 @@ struct Impl {
     hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid(kZChunkPhi), block, 0, c->stream, k, in.phi,
                        in.mu, out.phi, ts, tiles_x, tiles_y, kZChunkPhi);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
-    hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY>), grid(kZChunkMu), block, 0, c->stream, k, in.phi,
-                       out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y, kZChunkMu);
+    if (k.shrink)
+      hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY, true>), grid(kZChunkMu), block, 0, c->stream, k,
+                         in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y,
+                         kZChunkMu);
+    else
+      hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY, false>), grid(kZChunkMu), block, 0, c->stream, k,
+                         in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y,
+                         kZChunkMu);
     if (ev) (void)hipEventRecord(ev[2], c->stream);
   }
 
@@ -619,6 +630,8 @@ int validate(gpf_ctx* c, const gpf_grid* g, int N, int K, const gpf_params* p) {
                 p->lattice, g->dim);
   if (N < 2 || N > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_phases must be 2 or 3, got %d", N);
   if (K < 2 || K > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_components must be 2 or 3, got %d", K);
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->eta[a])) return fail(c, GPF_ERR_PARAM, "eta[%d] is not finite", a);
   if (p->precision != GPF_FP64 && p->precision != GPF_FP32)
     return fail(c, GPF_ERR_ARG, "unknown precision %d", p->precision);
   if (p->potential != GPF_OBSTACLE && p->potential != GPF_WELL)
@@ -1015,6 +1028,9 @@ int gpf_adjoint(gpf_ctx* c, const double* dL_dphi, size_t count, const char* con
   if (count != (size_t)c->N * (size_t)c->cells)
     return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, (size_t)c->N * (size_t)c->cells);
   if (n_names > gpf::NG) return fail(c, GPF_ERR_ARG, "at most %d parameters", gpf::NG);
+  for (int a = 0; a < 3; ++a)
+    if (c->prm.eta[a] != 0.0)
+      return fail(c, GPF_ERR_UNSUPPORTED, "the adjoint does not include the shrinkage force (eta != 0)");
   int slots[gpf::NG];
   for (int i = 0; i < n_names; ++i) {
     slots[i] = names[i] ? grad_slot(names[i]) : -1;

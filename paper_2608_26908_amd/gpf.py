@@ -51,7 +51,8 @@ class ParamsC(ctypes.Structure):
         ("tau_lb", ctypes.c_double), ("rho0", ctypes.c_double),
         ("gbeta", ctypes.c_double * 2), ("c_ref", ctypes.c_double * 2),
         ("grav_axis", ctypes.c_int32), ("grav_sign", ctypes.c_int32),
-        ("h_drag", ctypes.c_double), ("W0", ctypes.c_double), ("lid_u", ctypes.c_double),
+        ("h_drag", ctypes.c_double), ("W0", ctypes.c_double), ("eta", ctypes.c_double * 3),
+        ("lid_u", ctypes.c_double),
         ("init_kind", ctypes.c_int32), ("init_center", ctypes.c_double * 3),
         ("init_radius", ctypes.c_double), ("lam_width", ctypes.c_double),
         ("lam_height", ctypes.c_double), ("mu_inf", ctypes.c_double * 2),
@@ -133,6 +134,7 @@ def make_params(cfg, precision):
     for name in ("gamma", "delta", "chi", "c0", "dS", "D", "gbeta", "c_ref", "mu_inf"):
         _fill(getattr(p, name), cfg[name])
     _fill(p.init_center, cfg.get("init_center", [0.0, 0.0, 0.0]))
+    _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]))
     p.health_every = int(cfg.get("health_every", 0))
     return p
 
