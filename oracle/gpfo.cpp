@@ -45,15 +45,36 @@ const double PI = 3.14159265358979323846;
 
 struct Lattice {
   int Q;
-  int c[19][3];
-  double w[19];
-  int opp[19];
+  int c[27][3];
+  double w[27];
+  int opp[27];
 };
 
-Lattice make_lattice(int dim) {
+/* Q = 9 (2D), 19 or 27 (3D) */
+Lattice make_lattice_q(int Q) {
   Lattice L;
   std::memset(&L, 0, sizeof(L));
-  if (dim == 2) {
+  if (Q == 27) {
+    /* D3Q27 of Table LBM_Schemes: rest 8/27, 6 faces 2/27, 12 edges 1/54,
+     * 8 corners 1/216.  Numbering: the D3Q19 directions first (same order),
+     * then the corners in opposite pairs. */
+    L.Q = 27;
+    int k = 0;
+    const int order19[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                                {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    const int corners[8][3] = {{1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+                               {1, -1, 1}, {-1, 1, -1},  {-1, 1, 1}, {1, -1, -1}};
+    for (; k < 19; ++k)
+      for (int a = 0; a < 3; ++a) L.c[k][a] = order19[k][a];
+    for (int j = 0; j < 8; ++j, ++k)
+      for (int a = 0; a < 3; ++a) L.c[k][a] = corners[j][a];
+    for (k = 0; k < 27; ++k) {
+      int len2 = L.c[k][0] * L.c[k][0] + L.c[k][1] * L.c[k][1] + L.c[k][2] * L.c[k][2];
+      L.w[k] = len2 == 0 ? 8.0 / 27.0 : (len2 == 1 ? 2.0 / 27.0 : (len2 == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
+    }
+  } else if (Q == 9) {
     /* numbering of the paper's D2Q9 figure; weights 4/9, 1/9, 1/36 */
     const int c2[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
                           {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
@@ -84,6 +105,8 @@ Lattice make_lattice(int dim) {
         L.opp[j] = k;
   return L;
 }
+
+Lattice make_lattice(int dim) { return make_lattice_q(dim == 2 ? 9 : 19); }
 
 /* ---------------- parameters with the scalar type S ------------------------ */
 
@@ -355,13 +378,16 @@ S temperature(const Par<S>& p, const long* x, long nstep) {
 /* A(P): phases that are non-zero somewhere in the lattice neighbourhood of P
  * (9 points in 2D, 19 in 3D).  Reading of the multiplier Lambda: the simplex
  * projection acts only on these phases, so no phase can appear in a cell
- * none of its neighbours holds. */
+ * none of its neighbours holds.  With the D3Q27 lattice the phase-field
+ * neighbourhood stays the 19 points (the corners carry no phase-field
+ * coupling): the lattice only changes the populations. */
 template <class S>
 unsigned active_set(const Grid& g, const Lattice& L, const Par<S>& p, const State<S>& st,
                     const long* x) {
   unsigned mask = 0;
   long nc = g.cells();
   for (int k = 0; k < L.Q; ++k) {
+    if (L.c[k][0] != 0 && L.c[k][1] != 0 && L.c[k][2] != 0) continue;
     long j = g.field_nb(x, L.c[k]);
     for (int a = 0; a < p.N; ++a)
       if (re(st.phi[a * nc + j]) > 0.0) mask |= 1u << a;
@@ -686,7 +712,7 @@ void step_once(const Grid& g, const Lattice& L, const Par<S>& p, State<S>& st) {
   /* S5: collision at every cell with phi^{n+1}_l and mu^{n+1} */
 #pragma omp parallel for schedule(static)
   for (long P = 0; P < cells; ++P) {
-    S fin[19], fo[19], uo[3], mnew[2], GS[3];
+    S fin[27], fo[27], uo[3], mnew[2], GS[3];
     long x[3];
     g.coords(P, x);
     shrinkage_force(g, p, st.phi, phin, x, GS);
@@ -841,7 +867,7 @@ gpfo_sim* gpfo_create(const gpfo_params* p, uint64_t seed) {
   }
   s->prm.periodic[2] = s->g.periodic[2];
   if (p->dim == 2) s->prm.n[2] = 1;
-  s->L = make_lattice(p->dim);
+  s->L = (p->dim == 3 && p->lattice_q == 27) ? make_lattice_q(27) : make_lattice(p->dim);
   init_state(s, seed);
   return s;
 }
@@ -960,9 +986,9 @@ int gpfo_total(const gpfo_sim* s, int32_t which, double* out) {
   return -1;
 }
 
-int gpfo_lattice(int32_t dim, int32_t* c_out, double* w_out, int32_t* opp_out) {
-  if (dim != 2 && dim != 3) return -1;
-  Lattice L = make_lattice(dim);
+int gpfo_lattice(int32_t Q, int32_t* c_out, double* w_out, int32_t* opp_out) {
+  if (Q != 9 && Q != 19 && Q != 27) return -1;
+  Lattice L = make_lattice_q(Q);
   for (int k = 0; k < L.Q; ++k) {
     for (int a = 0; a < 3; ++a) c_out[3 * k + a] = L.c[k][a];
     w_out[k] = L.w[k];
@@ -993,12 +1019,14 @@ int gpfo_project(int32_t m, const double* v, double* out) {
   return 0;
 }
 void gpfo_interp_h(int32_t N, const double* phi, double* h, double* dh) { interp_h(N, phi, h, dh); }
-void gpfo_feq(int32_t dim, double rho, const double* u, double* out) {
-  Lattice L = make_lattice(dim);
+void gpfo_feq(int32_t Q, double rho, const double* u, double* out) {
+  Lattice L = make_lattice_q(Q);
+  const int dim = Q == 9 ? 2 : 3;
   for (int k = 0; k < L.Q; ++k) out[k] = feq(L, k, rho, u, dim);
 }
-void gpfo_guo(int32_t dim, double tau, const double* u, const double* F, double* S) {
-  Lattice L = make_lattice(dim);
+void gpfo_guo(int32_t Q, double tau, const double* u, const double* F, double* S) {
+  Lattice L = make_lattice_q(Q);
+  const int dim = Q == 9 ? 2 : 3;
   for (int k = 0; k < L.Q; ++k) S[k] = guo(L, k, tau, u, F, dim);
 }
 double gpfo_normal(uint64_t seed, uint64_t j) { return normal_j(seed, j); }

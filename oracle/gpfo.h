@@ -70,6 +70,7 @@ typedef struct {
   double lam_width, lam_height;
   double mu_inf[2], noise_sigma;
   double eta[3];          /* shrinkage: eta_a = (rho_a - rho_liq) / rho_liq (0: off) */
+  int32_t lattice_q;      /* 3D lattice: 27 for D3Q27, anything else D3Q19 */
 } gpfo_params;
 
 typedef struct gpfo_sim gpfo_sim;
@@ -94,7 +95,8 @@ int gpfo_set(gpfo_sim* s, int32_t field, const double* src);
 int gpfo_total(const gpfo_sim* s, int32_t which, double* out);
 
 /* Pointwise pieces, exposed for the unit pins. */
-int gpfo_lattice(int32_t dim, int32_t* c_out /* Q*3 */, double* w_out, int32_t* opp_out);
+/* lattice with Q = 9 (D2Q9), 19 (D3Q19) or 27 (D3Q27); returns Q, -1 otherwise */
+int gpfo_lattice(int32_t Q, int32_t* c_out /* Q*3 */, double* w_out, int32_t* opp_out);
 double gpfo_aniso_ac(int32_t dim, const double* q, double delta);
 double gpfo_aniso_A(int32_t dim, const double* q, double gamma, double delta);
 void gpfo_aniso_dAdq(int32_t dim, const double* q, double gamma, double delta, double* out);
@@ -104,8 +106,8 @@ void gpfo_aniso_dAdq_cs(int32_t dim, const double* q, double gamma, double delta
                         double h, double* out);
 int gpfo_project(int32_t m, const double* v, double* out);
 void gpfo_interp_h(int32_t N, const double* phi, double* h, double* dh /* N*N, dh[b*N+a] = dh_b/dphi_a */);
-void gpfo_feq(int32_t dim, double rho, const double* u, double* feq);
-void gpfo_guo(int32_t dim, double tau, const double* u, const double* F, double* S);
+void gpfo_feq(int32_t Q, double rho, const double* u, double* feq);
+void gpfo_guo(int32_t Q, double tau, const double* u, const double* F, double* S);
 double gpfo_normal(uint64_t seed, uint64_t j);
 
 /* Complex-step derivative of L = 1/2 sum (phi_T - target)^2 after nsteps

@@ -47,6 +47,7 @@ class _Params(ctypes.Structure):
         ("init_radius", ctypes.c_double), ("lam_width", ctypes.c_double),
         ("lam_height", ctypes.c_double), ("mu_inf", ctypes.c_double * 2),
         ("noise_sigma", ctypes.c_double), ("eta", ctypes.c_double * 3),
+        ("lattice_q", ctypes.c_int32),
     ]
 
 
@@ -145,6 +146,7 @@ def make_params(cfg):
     _fill(p.init_center, cfg.get("init_center", [0, 0, 0]), (3,))
     _fill(p.mu_inf, cfg["mu_inf"], (2,))
     _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]), (3,))
+    p.lattice_q = 27 if cfg.get("lattice") == "D3Q27" else 0
     return p
 
 
@@ -224,11 +226,16 @@ class OracleSim:
 
 # ----- pointwise functions --------------------------------------------------
 
-def lattice(dim):
-    c = np.zeros((19, 3), dtype=np.int32)
-    w = np.zeros(19)
-    opp = np.zeros(19, dtype=np.int32)
-    Q = lib().gpfo_lattice(dim, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(w),
+def _q(dim, Q):
+    return Q if Q else (9 if dim == 2 else 19)
+
+
+def lattice(dim, Q=None):
+    """(c, w, opp) of D2Q9 (dim 2), D3Q19 (dim 3) or D3Q27 (dim 3, Q = 27)."""
+    c = np.zeros((27, 3), dtype=np.int32)
+    w = np.zeros(27)
+    opp = np.zeros(27, dtype=np.int32)
+    Q = lib().gpfo_lattice(_q(dim, Q), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(w),
                            opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return c[:Q, :dim].copy(), w[:Q].copy(), opp[:Q].copy()
 
@@ -272,19 +279,19 @@ def interp_h(phi):
     return h, dh.reshape(N, N)
 
 
-def feq(dim, rho, u):
+def feq(dim, rho, u, Q=None):
     u = np.ascontiguousarray(u, dtype=float)
-    out = np.zeros(19)
-    lib().gpfo_feq(dim, rho, _dp(u), _dp(out))
-    return out[: (9 if dim == 2 else 19)]
+    out = np.zeros(27)
+    lib().gpfo_feq(_q(dim, Q), rho, _dp(u), _dp(out))
+    return out[: _q(dim, Q)]
 
 
-def guo(dim, tau, u, F):
+def guo(dim, tau, u, F, Q=None):
     u = np.ascontiguousarray(u, dtype=float)
     F = np.ascontiguousarray(F, dtype=float)
-    out = np.zeros(19)
-    lib().gpfo_guo(dim, tau, _dp(u), _dp(F), _dp(out))
-    return out[: (9 if dim == 2 else 19)]
+    out = np.zeros(27)
+    lib().gpfo_guo(_q(dim, Q), tau, _dp(u), _dp(F), _dp(out))
+    return out[: _q(dim, Q)]
 
 
 def normal(seed, j):

@@ -21,7 +21,13 @@ H_CS = 1e-30
 PI = math.pi
 
 
-def lattice(dim):
+def lattice(dim, kind=None):
+    if kind == "D3Q27":
+        # the paper's Table LBM_Schemes: rest 8/27, faces 2/27, edges 1/54,
+        # corners 1/216; every velocity of {-1, 0, 1}^3, ordered by length
+        c = sorted(itertools.product((-1, 0, 1), repeat=3), key=lambda v: sum(x * x for x in v))
+        wmap = {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}
+        return c, [wmap[sum(x * x for x in v)] for v in c]
     if dim == 2:
         order = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
         c = [tuple(v) + (0,) for v in order]
@@ -91,7 +97,7 @@ class Step:
         self.n = list(cfg["n"][: self.dim])
         self.per = list(cfg["periodic"][: self.dim])
         self.N, self.nc = cfg["N"], cfg["nc"]
-        self.c, self.w = lattice(self.dim)
+        self.c, self.w = lattice(self.dim, cfg.get("lattice"))
         self.Q = len(self.c)
 
     # ----- index helpers (x = (x, y[, z]) tuple) -----
@@ -199,7 +205,8 @@ class Step:
                 div[x][al] += J[al] / dx
                 div[y][al] -= J[al] / dx
         new = np.array(st["phi"], dtype=float)
-        offs = [o[: d] for o in self.c]
+        # phase-field neighbourhood: the 9 / 19 points (no 3D corners)
+        offs = [o[: d] for o in self.c if sum(1 for v in o if v) < 3]
         for x in self.cells():
             act = [b for b in range(N) if any(self.phi(st, b, self.add(x, o)) > 0 for o in offs)]
             if len(act) <= 1:

@@ -6,6 +6,7 @@ from paper_2608_26908_amd.workloads import workload
 
 D2Q9_W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 D3Q19_W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+D3Q27_W = np.array([8 / 27] + [2 / 27] * 6 + [1 / 54] * 12 + [1 / 216] * 8)
 
 
 def random_state(cfg, seed):
@@ -15,7 +16,7 @@ def random_state(cfg, seed):
     rng = np.random.default_rng(seed)
     dim, N, nc = cfg["dim"], cfg["N"], cfg["nc"]
     shape = tuple(reversed(cfg["n"][:dim]))
-    w = D2Q9_W if dim == 2 else D3Q19_W
+    w = D2Q9_W if dim == 2 else (D3Q27_W if cfg.get("lattice") == "D3Q27" else D3Q19_W)
     kind = rng.uniform(size=shape)
     mixed = rng.dirichlet(np.ones(N), size=shape)  # (..., N)
     phi = np.moveaxis(mixed, -1, 0).copy()

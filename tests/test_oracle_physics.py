@@ -23,7 +23,7 @@ def liquid_box(dim, n, periodic, **kw):
 def set_equilibrium_flow(sim, oracle, u):
     """f = f^eq(rho0, u) per cell and U^{n-1} = u; u has shape (dim, *grid)."""
     dim = sim.dim
-    c, w, _ = oracle.lattice(dim)
+    c, w, _ = oracle.lattice(dim, sim.Q)
     uu = (u ** 2).sum(0)
     cu = np.tensordot(c.astype(float), u, axes=(1, 0))
     f = w.reshape((-1,) + (1,) * dim) * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * uu)
@@ -279,6 +279,29 @@ def test_shear_wave_decay_gives_viscosity(oracle):
     s.step(1000)
     a2 = s.get("u")[0][:, 0] @ np.sin(k * y)
     nu_meas = -math.log(a2 / a1) / (1000 * k * k)
+    assert nu_meas == pytest.approx((tau - 0.5) / 3, rel=2e-3)
+
+
+@pytest.mark.parametrize("lattice", ["D3Q19", "D3Q27"])
+def test_shear_wave_decay_3d(oracle, lattice):
+    """The same decay in 3D, U_x = A sin(k z), on both 3D lattices (D3Q27 is
+    the paper's, Table LBM_Schemes): the viscosity is (tau - 1/2)/3 for
+    either velocity set."""
+    n = 48
+    tau = 0.9
+    cfg = liquid_box(3, [2, 2, n], [1, 1, 1], tau_lb=tau, lattice=lattice)
+    s = oracle.OracleSim(cfg)
+    assert s.Q == (27 if lattice == "D3Q27" else 19)
+    k = 2 * math.pi / n
+    z = np.arange(n)
+    u = np.zeros((3, n, 2, 2))
+    u[0] = (1e-4 * np.sin(k * z))[:, None, None]
+    set_equilibrium_flow(s, oracle, u)
+    s.step(1)
+    a1 = s.get("u")[0][:, 0, 0] @ np.sin(k * z)
+    s.step(600)
+    a2 = s.get("u")[0][:, 0, 0] @ np.sin(k * z)
+    nu_meas = -math.log(a2 / a1) / (600 * k * k)
     assert nu_meas == pytest.approx((tau - 0.5) / 3, rel=2e-3)
 
 

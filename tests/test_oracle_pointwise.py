@@ -35,13 +35,26 @@ def test_d2q9_matches_paper_table(oracle):
         assert np.all(c[opp[k]] == -c[k])
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_lattice_isotropy(oracle, dim):
+def test_d3q27_matches_paper_table(oracle):
+    c, w, opp = oracle.lattice(3, 27)
+    rows = _read_table("lattice_d3q27.txt")
+    assert len(w) == 27
+    for k0, k1, len2, wk in rows:
+        for k in range(int(k0), int(k1) + 1):
+            assert int((c[k] ** 2).sum()) == int(len2)
+            assert w[k] == pytest.approx(float(Fraction(wk)), abs=1e-16)
+    assert len({tuple(v) for v in c}) == 27
+
+
+LATTICES = [(2, 9), (3, 19), (3, 27)]
+
+
+@pytest.mark.parametrize("dim,Q", LATTICES)
+def test_lattice_isotropy(oracle, dim, Q):
     """Unity sum, symmetry and isotropy of the weights (App. A requires
     them); 2nd moment c_s^2 I with c_s^2 = 1/3, 4th moment isotropic."""
-    c, w, opp = oracle.lattice(dim)
-    Q = len(w)
-    assert Q == (9 if dim == 2 else 19)
+    c, w, opp = oracle.lattice(dim, Q)
+    assert len(w) == Q
     assert len({tuple(v) for v in c}) == Q
     assert w.sum() == pytest.approx(1.0, abs=1e-15)
     assert np.abs((w[:, None] * c).sum(0)).max() < 1e-16
@@ -61,30 +74,30 @@ def test_lattice_isotropy(oracle, dim):
 
 # ---------------- equilibrium and forcing moments --------------------------
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_feq_moments(oracle, dim):
-    c, w, _ = oracle.lattice(dim)
+@pytest.mark.parametrize("dim,Q", LATTICES)
+def test_feq_moments(oracle, dim, Q):
+    c, w, _ = oracle.lattice(dim, Q)
     rng = np.random.default_rng(3)
     for _ in range(5):
         rho = 1.0 + 0.1 * rng.standard_normal()
         u = 0.05 * rng.standard_normal(dim)
-        f = oracle.feq(dim, rho, np.pad(u, (0, 3 - dim)))
+        f = oracle.feq(dim, rho, np.pad(u, (0, 3 - dim)), Q)
         assert f.sum() == pytest.approx(rho, abs=1e-15)
         assert np.abs(c.T @ f - rho * u).max() < 1e-16
         P = np.einsum("k,ka,kb->ab", f, c, c)
         assert np.abs(P - rho * (np.eye(dim) / 3.0 + np.outer(u, u))).max() < 1e-15
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_guo_source_moments(oracle, dim):
+@pytest.mark.parametrize("dim,Q", LATTICES)
+def test_guo_source_moments(oracle, dim, Q):
     """Discrete force, read as Guo's scheme: zeroth moment 0, first
     (1 - 1/2tau) F, second (1 - 1/2tau)(uF + Fu)."""
-    c, w, _ = oracle.lattice(dim)
+    c, w, _ = oracle.lattice(dim, Q)
     rng = np.random.default_rng(4)
     for tau in (0.6, 0.8, 1.3):
         u = 0.05 * rng.standard_normal(dim)
         F = 1e-3 * rng.standard_normal(dim)
-        S = oracle.guo(dim, tau, np.pad(u, (0, 3 - dim)), np.pad(F, (0, 3 - dim)))
+        S = oracle.guo(dim, tau, np.pad(u, (0, 3 - dim)), np.pad(F, (0, 3 - dim)), Q)
         pref = 1.0 - 0.5 / tau
         assert abs(S.sum()) < 1e-18
         assert np.abs(c.T @ S - pref * F).max() < 1e-18
