@@ -29,7 +29,7 @@ def bytes_per_lup(cfg, s):
     """Algorithmic bytes per lattice update: the state read once and written
     once, phi counted N-1 times (sum phi = 1), U and T derived:
     2 (N - 1 + nc + Q) s."""
-    Q = 9 if cfg["dim"] == 2 else 19
+    Q = 9 if cfg["dim"] == 2 else (27 if cfg.get("lattice") == "D3Q27" else 19)
     return 2 * (cfg["N"] - 1 + cfg["nc"] + Q) * s
 
 
@@ -207,6 +207,11 @@ def main():
                  args.warmup)
     print(f"# fp32 with shrinkage: {rs['mlups']:.1f} MLUPS, {rs['ms_per_step']:.3f} ms/step",
           file=sys.stderr, flush=True)
+    # the paper's own 3D lattice, D3Q27 (Table LBM_Schemes), on the same workload
+    c27 = workload(args.workload, lattice="D3Q27")
+    r27 = run_gpu(c27, "fp32", min(args.steps, 100), args.warmup)
+    print(f"# fp32 D3Q27: {r27['mlups']:.1f} MLUPS, {r27['ms_per_step']:.3f} ms/step", file=sys.stderr,
+          flush=True)
     copy_gbs = copy_bandwidth()
     print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     b32 = bytes_per_lup(cfg, 4)
@@ -243,6 +248,12 @@ def main():
     line["shrinkage"] = {"value": round(rs["mlups"], 2), "unit": "MLUPS", "eta": [0.2, 0.0, 0.0],
                          "ms_per_step": round(rs["ms_per_step"], 4),
                          "k_phi_ms": round(rs["k_phi_ms"], 4), "k_mulbm_ms": round(rs["k_mulbm_ms"], 4)}
+    b27 = bytes_per_lup(c27, 4)
+    line["d3q27"] = {"value": round(r27["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(r27["ms_per_step"], 4),
+                     "k_phi_ms": round(r27["k_phi_ms"], 4), "k_mulbm_ms": round(r27["k_mulbm_ms"], 4),
+                     "bytes_per_lup": b27,
+                     "roofline_frac": round(b27 * cells / (r27["k_mulbm_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "step_frac": round(b27 * cells / (r27["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if r64:
         b64 = bytes_per_lup(cfg, 8)
         line["fp64"] = {"value": round(r64["mlups"], 2), "unit": "MLUPS",

@@ -11,10 +11,13 @@
  *      (the paper's modification; U = 0 in solids);
  *   3. one BGK collide + stream, Eq. (LBMEq_1) with f^eq of Eq. (f^eq) and
  *      the discrete force of Eq. (discreteForce), carrying the solutal
- *      buoyancy of Eq. (buoyancy) and the drag force G_D that enforces
- *      no-slip at the diffuse solid-liquid interface;
+ *      buoyancy of Eq. (buoyancy), the drag force G_D that enforces
+ *      no-slip at the diffuse solid-liquid interface and, when enabled, the
+ *      shrinkage force of Eq. (shrinkage);
  *   4. staggered in the order of Algorithm phfLBM (App. A).
- * D2Q9 (Table LBM_Schemes) in 2D, D3Q19 in 3D.
+ * D2Q9 (Table LBM_Schemes) in 2D; D3Q19 or D3Q27 (Table LBM_Schemes) in 3D.
+ * The lattice changes only the populations: the phase-field and
+ * chemical-potential stencils use the 9/19-point neighbourhood throughout.
  *
  * Conventions for every call:
  *   - Return value: a gpf_status; GPF_OK = 0, negative on error.  No C++
@@ -25,7 +28,9 @@
  *   - Lattice numbering: D2Q9 as in the paper's lattice figure (0 rest,
  *     1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-)); D3Q19:
  *     0 rest, 1..6 = +x,-x,+y,-y,+z,-z, then (+,+,0),(-,-,0),(+,-,0),(-,+,0),
- *     (+,0,+),(-,0,-),(+,0,-),(-,0,+),(0,+,+),(0,-,-),(0,+,-),(0,-,+).
+ *     (+,0,+),(-,0,-),(+,0,-),(-,0,+),(0,+,+),(0,-,-),(0,+,-),(0,-,+);
+ *     D3Q27: the D3Q19 order, then (+,+,+),(-,-,-),(+,+,-),(-,-,+),(+,-,+),
+ *     (-,+,-),(-,+,+),(+,-,-).
  *   - Phases: solids first, liquid last.  n_components = K counts all
  *     species, so there are nc = K - 1 independent chemical potentials.
  *   - A context owns its device buffers; every host pointer passed in
@@ -54,7 +59,8 @@ typedef enum {
   GPF_ERR_UNSUPPORTED = -7  /* valid but not built: (dim, lattice, N, nc) outside the instances */
 } gpf_status;
 
-typedef enum { GPF_D2Q9 = 0, GPF_D3Q19 = 1 } gpf_lattice;
+/* D2Q9 in 2D; D3Q19, or the paper's D3Q27 (Table LBM_Schemes), in 3D */
+typedef enum { GPF_D2Q9 = 0, GPF_D3Q19 = 1, GPF_D3Q27 = 2 } gpf_lattice;
 typedef enum { GPF_FP64 = 0, GPF_FP32 = 1 } gpf_precision;
 typedef enum { GPF_OBSTACLE = 0, GPF_WELL = 1 } gpf_potential;
 typedef enum { GPF_INIT_SEED = 0, GPF_INIT_LAMELLAE = 1, GPF_INIT_LIQUID = 2 } gpf_init_kind;

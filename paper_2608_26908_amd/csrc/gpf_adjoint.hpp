@@ -89,13 +89,13 @@ __device__ __forceinline__ R d2h(const R (&ph)[N], int b, int a, int g) {
 // TAPE: rho - rho0 of the step was stored by the forward recomputation and U
 // is the step's own output, so f is not read; otherwise both are recomputed
 // from the pulled f (the last step of a checkpoint segment).
-template <int D, int N, int NC, class R, bool TAPE>
+template <int D, int Q, int N, int NC, class R, bool TAPE>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
           const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
           const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
           R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
-  using L = Lat<D>;
+  using L = Lat<Q>;
   const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
   if (P < p.cells) {
@@ -104,7 +104,7 @@ k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const 
     R f[TAPE ? 1 : L::Q], ob[L::Q];
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-      if constexpr (!TAPE) f[k] = pull_f<D, R>(p, fst, x, y, z, P, k);
+      if constexpr (!TAPE) f[k] = pull_f<D, Q, R>(p, fst, x, y, z, P, k);
       // f*_k(P) streams to f_k(P + c_k), or is reflected into f_{opp k}(P)
       int dst[3] = {x + L::c(k, 0), y + L::c(k, 1), z + L::c(k, 2)};
       bool in = true;

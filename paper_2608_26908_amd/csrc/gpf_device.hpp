@@ -16,9 +16,9 @@ namespace gpf {
 // 3D lattice is D3Q27).  The neighbourhood a cell update reads is the same
 // set of offsets, so one table serves the stencils and the streaming.
 // ---------------------------------------------------------------------------
-template <int D> struct Lat;
+template <int Q> struct Lat;
 
-template <> struct Lat<2> {
+template <> struct Lat<9> {
   static constexpr int Q = 9;
   __host__ __device__ static constexpr int c(int k, int a) {
     constexpr int t[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
@@ -34,7 +34,7 @@ template <> struct Lat<2> {
   }
 };
 
-template <> struct Lat<3> {
+template <> struct Lat<19> {
   static constexpr int Q = 19;
   __host__ __device__ static constexpr int c(int k, int a) {
     constexpr int t[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
@@ -49,6 +49,29 @@ template <> struct Lat<3> {
   }
   __host__ __device__ static constexpr double w(int k) {
     return k == 0 ? 1.0 / 3.0 : (k <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+};
+
+// D3Q27 of Table LBM_Schemes: the D3Q19 directions in the same order, then
+// the 8 corners in opposite pairs; weights 8/27, 2/27, 1/54, 1/216
+template <> struct Lat<27> {
+  static constexpr int Q = 27;
+  __host__ __device__ static constexpr int c(int k, int a) {
+    constexpr int t[27][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                              {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                              {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                              {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+                              {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+                              {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+    return t[k][a];
+  }
+  __host__ __device__ static constexpr int opp(int k) {
+    constexpr int t[27] = {0,  2,  1,  4,  3,  6,  5,  8,  7,  10, 9,  12, 11, 14,
+                           13, 16, 15, 18, 17, 20, 19, 22, 21, 24, 23, 26, 25};
+    return t[k];
+  }
+  __host__ __device__ static constexpr double w(int k) {
+    return k == 0 ? 8.0 / 27.0 : (k <= 6 ? 2.0 / 27.0 : (k <= 18 ? 1.0 / 54.0 : 1.0 / 216.0));
   }
 };
 
@@ -75,7 +98,7 @@ template <class R> struct KP {
   R eta[3];               // shrinkage (rho_a - rho_liq) / rho_liq per phase
   int shrink;             // some eta != 0
   R qmin2;                // |q|^2 below which the anisotropy direction is undefined
-  R w[19];                // lattice weights in R
+  R w[27];                // lattice weights in R
 };
 
 // ---------------------------------------------------------------------------

@@ -20,10 +20,10 @@ namespace gpf {
 // when that cell lies behind a wall, the reflected f*_{opp k}(P) (half-way
 // bounce-back; the wall sits on the zero-flux face of phi and mu).  The
 // test-only moving upper wall of axis 1 adds 6 w_k rho0 c_k . U_wall.
-template <int D, class R>
+template <int D, int Q, class R>
 __device__ __forceinline__ R pull_f(const KP<R>& p, const R* __restrict__ fin, int x, int y, int z,
                                     int64_t P, int k) {
-  using L = Lat<D>;
+  using L = Lat<Q>;
   int src[3] = {x - L::c(k, 0), y - L::c(k, 1), z - L::c(k, 2)};
   bool in = true;
 #pragma unroll
@@ -37,7 +37,7 @@ __device__ __forceinline__ R pull_f(const KP<R>& p, const R* __restrict__ fin, i
     }
   }
   if (in) return fin[k * p.cells + (int64_t)src[2] * p.sz + (int64_t)src[1] * p.sy + src[0]];
-  R val = fin[Lat<D>::opp(k) * p.cells + P];
+  R val = fin[Lat<Q>::opp(k) * p.cells + P];
   if (L::c(k, 1) < 0 && !p.per[1] && y - L::c(k, 1) >= p.n[1])
     val += R(6) * p.w[k] * p.rho0 * R(L::c(k, 0)) * p.lid_u;
   return val;
@@ -228,7 +228,7 @@ __device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N]
 // ---------------------------------------------------------------------------
 // SH: the shrinkage force is on (a separate instance keeps the registers of
 // the common case unchanged)
-template <int D, int N, int NC, class R, bool SH>
+template <int D, int Q, int N, int NC, class R, bool SH>
 __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
                                            const R (&ph1n)[2 * D + 1][N],
                                            const R (&mun)[2 * D + 1][NC], const R (&uc)[D],
@@ -236,7 +236,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
                                            const R* __restrict__ fin, R* __restrict__ mu_out,
                                            R* __restrict__ u_out, R* __restrict__ fout,
                                            R* __restrict__ dr_out) {
-  using L = Lat<D>;
+  using L = Lat<Q>;
   const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
   const int pos[3] = {x, y, z};
 
@@ -331,7 +331,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
   // ---- LBM: pull streaming of the previous post-collision populations ----
   R f[L::Q];
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) f[k] = pull_f<D, R>(p, fin, x, y, z, P, k);
+  for (int k = 0; k < L::Q; ++k) f[k] = pull_f<D, Q, R>(p, fin, x, y, z, P, k);
   // moments (deviation storage: rho = rho0 + sum f~, momentum = sum f~ c)
   R dr = R(0), mom[D];
 #pragma unroll
@@ -551,7 +551,7 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
 // barrier per plane.  Threads past the grid's edge hold the wrapped (periodic)
 // or clamped (wall) column, which only serves as a neighbour.
 // ---------------------------------------------------------------------------
-template <int D, int N, int NC, class R, int TX, int TY, bool SH>
+template <int D, int Q, int N, int NC, class R, int TX, int TY, bool SH>
 __global__ void __launch_bounds__(TX * TY)
 k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
@@ -686,7 +686,7 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
         un[D - 1][0] = cuz[0];
         un[D - 1][1] = cuz[2];
       }
-      mulbm_core<D, N, NC, R, SH>(p, xq, yq, z, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout, dr_out);
+      mulbm_core<D, Q, N, NC, R, SH>(p, xq, yq, z, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout, dr_out);
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
@@ -713,22 +713,22 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
 // ---------------------------------------------------------------------------
 
 // f^n_k(P) = stored f*_k(P - c_k) (+ bounce-back), plus w_k rho0: the full f.
-template <int D, class R>
+template <int D, int Q, class R>
 __global__ void k_gather_f(KP<R> p, const R* __restrict__ fin, double* __restrict__ out) {
-  using L = Lat<D>;
+  using L = Lat<Q>;
   const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (P >= p.cells) return;
   const int x = (int)(P % p.n[0]);
   const int y = (int)((P / p.sy) % p.n[1]);
   const int z = (int)(P / p.sz);
   for (int k = 0; k < L::Q; ++k)
-    out[k * p.cells + P] = (double)pull_f<D, R>(p, fin, x, y, z, P, k) + L::w(k) * (double)p.rho0;
+    out[k * p.cells + P] = (double)pull_f<D, Q, R>(p, fin, x, y, z, P, k) + L::w(k) * (double)p.rho0;
 }
 
 // inverse of k_gather_f: the stored pre-streaming f* that streams to f^n
-template <int D, class R>
+template <int D, int Q, class R>
 __global__ void k_scatter_f(KP<R> p, const double* __restrict__ fn, R* __restrict__ fst) {
-  using L = Lat<D>;
+  using L = Lat<Q>;
   const int64_t Qc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (Qc >= p.cells) return;
   const int x = (int)(Qc % p.n[0]);
@@ -791,11 +791,11 @@ __global__ void k_mu_native(const R* __restrict__ in, R* __restrict__ out, int64
 
 // derived per-cell fields in FP64: 0 rho, 1 mixture composition C (nc comps),
 // 2 temperature, 3 active-set bitmask
-template <int D, int N, int NC, class R>
+template <int D, int Q, int N, int NC, class R>
 __global__ void k_derived(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ mu,
                           const double* __restrict__ fgathered, double tshift_d,
                           double* __restrict__ out) {
-  using L = Lat<D>;
+  using L = Lat<Q>;
   const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (P >= p.cells) return;
   const int x = (int)(P % p.n[0]);
@@ -839,11 +839,11 @@ __global__ void k_derived(KP<R> p, int which, const R* __restrict__ phi, const R
 
 // FP64 block partial sums in a fixed order: solute (NC values) or mass.
 constexpr int RED_BLOCK = 256;
-template <int D, int N, int NC, class R>
+template <int D, int Q, int N, int NC, class R>
 __global__ void __launch_bounds__(RED_BLOCK)
 k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ mu,
           const R* __restrict__ f, double* __restrict__ partial) {
-  using L = Lat<D>;
+  using L = Lat<Q>;
   __shared__ double sh[NC][RED_BLOCK];
   const int t = threadIdx.x;
   double acc[NC];
@@ -870,7 +870,7 @@ k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ m
       const int z = (int)(P / p.sz);
       double r = 0.0;
       for (int k = 0; k < L::Q; ++k)
-        r += (double)pull_f<D, R>(p, f, x, y, z, P, k) + L::w(k) * (double)p.rho0;
+        r += (double)pull_f<D, Q, R>(p, f, x, y, z, P, k) + L::w(k) * (double)p.rho0;
       acc[0] += r;
     }
   }
@@ -903,11 +903,11 @@ __global__ void k_final_sum(const double* __restrict__ partial, int nblocks, int
 }
 
 // health: NaN/Inf in phi or mu, or rho <= 0, records the smallest step seen
-template <int D, int N, int NC, class R>
+template <int D, int Q, int N, int NC, class R>
 __global__ void k_health(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu,
                          const R* __restrict__ f, unsigned long long step,
                          unsigned long long* __restrict__ bad_step) {
-  using L = Lat<D>;
+  using L = Lat<Q>;
   const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (P >= p.cells) return;
   const int x = (int)(P % p.n[0]);
@@ -917,7 +917,7 @@ __global__ void k_health(KP<R> p, const R* __restrict__ phi, const R* __restrict
   for (int b = 0; b < N; ++b) bad |= !isfinite(phi[b * p.cells + P]);
   for (int i = 0; i < NC; ++i) bad |= !isfinite(mu[i * p.cells + P]);
   R r = p.rho0;
-  for (int k = 0; k < L::Q; ++k) r += pull_f<D, R>(p, f, x, y, z, P, k);
+  for (int k = 0; k < L::Q; ++k) r += pull_f<D, Q, R>(p, f, x, y, z, P, k);
   bad |= !(r > R(0));
   if (bad) atomicMin(bad_step, step);
 }

@@ -121,6 +121,11 @@ void dev_release(gpf_ctx* c, DevBuf& b) {
 // ---------------------------------------------------------------------------
 // kernel parameter block
 // ---------------------------------------------------------------------------
+// lattice weight w_k of D2Q9 (Q = 9), D3Q19 or D3Q27
+double lattice_w(int Q, int k) {
+  return Q == 9 ? gpf::Lat<9>::w(k) : (Q == 19 ? gpf::Lat<19>::w(k) : gpf::Lat<27>::w(k));
+}
+
 template <class R>
 gpf::KP<R> make_kp(const gpf_ctx* c) {
   const gpf_params& p = c->prm;
@@ -186,7 +191,7 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
   }
   k.qmin2 = (sizeof(R) == 8) ? (R)1e-24 : (R)1e-12;
   for (int q = 0; q < c->Q; ++q)
-    k.w[q] = (R)((c->dim == 2) ? gpf::Lat<2>::w(q) : gpf::Lat<3>::w(q));
+    k.w[q] = (R)lattice_w(c->Q, q);
   return k;
 }
 
@@ -223,14 +228,14 @@ inline unsigned lin_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 #endif
 constexpr int kTileY = GPF_TILE_Y, kZChunkPhi = GPF_ZCHUNK_PHI, kZChunkMu = GPF_ZCHUNK_MU;
 
-template <int D, int N, int NC, class R>
+template <int D, int Q, int N, int NC, class R>
 struct Impl {
   static R* P(DevBuf& b) { return static_cast<R*>(b.ptr); }
 
   static int health(gpf_ctx* c) {
     gpf::KP<R> k = make_kp<R>(c);
     const int s = c->cur;
-    hipLaunchKernelGGL((gpf::k_health<D, N, NC, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0,
+    hipLaunchKernelGGL((gpf::k_health<D, Q, N, NC, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0,
                        c->stream, k, P(c->phi[s]), P(c->mu[s]), P(c->f[s]),
                        (unsigned long long)c->step,
                        static_cast<unsigned long long*>(c->badstep.ptr));
@@ -260,11 +265,11 @@ struct Impl {
                        in.mu, out.phi, ts, tiles_x, tiles_y, kZChunkPhi);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
     if (k.shrink)
-      hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY, true>), grid(kZChunkMu), block, 0, c->stream, k,
+      hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, true>), grid(kZChunkMu), block, 0, c->stream, k,
                          in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y,
                          kZChunkMu);
     else
-      hipLaunchKernelGGL((gpf::k_mulbm_z<D, N, NC, R, TX, TY, false>), grid(kZChunkMu), block, 0, c->stream, k,
+      hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, false>), grid(kZChunkMu), block, 0, c->stream, k,
                          in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y,
                          kZChunkMu);
     if (ev) (void)hipEventRecord(ev[2], c->stream);
@@ -330,18 +335,18 @@ struct Impl {
       hipLaunchKernelGGL((gpf::k_to_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, src,
                          out, cnt);
     } else if (field == GPF_FPOST) {
-      ncomp = gpf::Lat<D>::Q;
+      ncomp = Q;
       const int64_t cnt = ncomp * c->cells;
       hipLaunchKernelGGL((gpf::k_to_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream,
                          P(c->f[s]), out, cnt);
     } else if (field == GPF_F || field == GPF_RHO) {
-      ncomp = (field == GPF_F) ? gpf::Lat<D>::Q : 1;
-      hipLaunchKernelGGL((gpf::k_gather_f<D, R>), dim3(nb), dim3(256), 0, c->stream, k, P(c->f[s]),
+      ncomp = (field == GPF_F) ? Q : 1;
+      hipLaunchKernelGGL((gpf::k_gather_f<D, Q, R>), dim3(nb), dim3(256), 0, c->stream, k, P(c->f[s]),
                          out);
       if (field == GPF_RHO) {
         // rho into the slot after the Q populations, then move to the front
-        double* rho = out + (int64_t)gpf::Lat<D>::Q * c->cells;
-        hipLaunchKernelGGL((gpf::k_derived<D, N, NC, R>), dim3(nb), dim3(256), 0, c->stream, k, 0,
+        double* rho = out + (int64_t)Q * c->cells;
+        hipLaunchKernelGGL((gpf::k_derived<D, Q, N, NC, R>), dim3(nb), dim3(256), 0, c->stream, k, 0,
                            P(c->phi[s]), P(c->mu[s]), out, 0.0, rho);
         HIP_OR_FAIL(c, hipMemcpyAsync(out, rho, c->cells * sizeof(double), hipMemcpyDeviceToDevice,
                                       c->stream));
@@ -349,7 +354,7 @@ struct Impl {
     } else if (field == GPF_C || field == GPF_T || field == GPF_FLAGS) {
       const int which = field == GPF_C ? 1 : field == GPF_T ? 2 : 3;
       ncomp = field == GPF_C ? NC : 1;
-      hipLaunchKernelGGL((gpf::k_derived<D, N, NC, R>), dim3(nb), dim3(256), 0, c->stream, k, which,
+      hipLaunchKernelGGL((gpf::k_derived<D, Q, N, NC, R>), dim3(nb), dim3(256), 0, c->stream, k, which,
                          P(c->phi[s]), P(c->mu[s]), out, tshift(c, c->step), out);
     } else {
       return fail(c, GPF_ERR_ARG, "unknown field %d", field);
@@ -378,7 +383,7 @@ struct Impl {
         double comps = 0;
         int rc = read(c, GPF_F, &comps);
         if (rc) return rc;
-        const int64_t cnt = gpf::Lat<D>::Q * c->cells;
+        const int64_t cnt = Q * c->cells;
         hipLaunchKernelGGL((gpf::k_from_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0,
                            c->stream, static_cast<const double*>(c->scratch.ptr), static_cast<R*>(dst), cnt);
         HIP_OR_FAIL(c, hipGetLastError());
@@ -396,11 +401,11 @@ struct Impl {
     const int s = c->cur;
     const double* in = static_cast<const double*>(c->scratch.ptr);
     if (field == GPF_FPOST) {
-      const int64_t cnt = gpf::Lat<D>::Q * c->cells;
+      const int64_t cnt = Q * c->cells;
       hipLaunchKernelGGL((gpf::k_from_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, in,
                          P(c->f[s]), cnt);
     } else if (field == GPF_F) {
-      hipLaunchKernelGGL((gpf::k_scatter_f<D, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0,
+      hipLaunchKernelGGL((gpf::k_scatter_f<D, Q, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0,
                          c->stream, k, in, P(c->f[s]));
     } else if (field == GPF_MU) {
       const int64_t cnt = NC * c->cells;
@@ -422,7 +427,7 @@ struct Impl {
     const int s = c->cur;
     const int nblk = (int)std::min<int64_t>(2048, lin_blocks(c->cells, gpf::RED_BLOCK));
     const int ncomp = which == GPF_SUM_SOLUTE ? NC : 1;
-    hipLaunchKernelGGL((gpf::k_partial<D, N, NC, R>), dim3(nblk), dim3(gpf::RED_BLOCK), 0, c->stream, k,
+    hipLaunchKernelGGL((gpf::k_partial<D, Q, N, NC, R>), dim3(nblk), dim3(gpf::RED_BLOCK), 0, c->stream, k,
                        which == GPF_SUM_SOLUTE ? 0 : 1, P(c->phi[s]), P(c->mu[s]), P(c->f[s]),
                        static_cast<double*>(c->partial.ptr));
     hipLaunchKernelGGL(gpf::k_final_sum, dim3(1), dim3(gpf::RED_BLOCK), 0, c->stream,
@@ -441,7 +446,7 @@ struct Impl {
     int rc = dev_alloc(c, s.phi, N * cs);
     if (!rc) rc = dev_alloc(c, s.mu, NC * cs);
     if (!rc) rc = dev_alloc(c, s.u, D * cs);
-    if (!rc) rc = dev_alloc(c, s.f, gpf::Lat<D>::Q * cs);
+    if (!rc) rc = dev_alloc(c, s.f, Q * cs);
     return rc;
   }
   static int copy_state(gpf_ctx* c, const StateBuf& dst, const StateBuf& src) {
@@ -475,10 +480,10 @@ struct Impl {
     const int64_t pstride = (int64_t)nb * gpf::NG;
     const dim3 g(nb), b(gpf::ADJ_BLOCK);
     if (x1.dr)
-      hipLaunchKernelGGL((gpf::k_adj_lbm<D, N, NC, R, true>), g, b, 0, c->stream, k, x0.f, x1.dr, x1.u, x1.phi,
+      hipLaunchKernelGGL((gpf::k_adj_lbm<D, Q, N, NC, R, true>), g, b, 0, c->stream, k, x0.f, x1.dr, x1.u, x1.phi,
                          x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu), part);
     else
-      hipLaunchKernelGGL((gpf::k_adj_lbm<D, N, NC, R, false>), g, b, 0, c->stream, k, x0.f, x1.dr, x1.u,
+      hipLaunchKernelGGL((gpf::k_adj_lbm<D, Q, N, NC, R, false>), g, b, 0, c->stream, k, x0.f, x1.dr, x1.u,
                          x1.phi, x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu),
                          part);
     uint8_t* rflag = static_cast<uint8_t*>(c->t_rflag.ptr);
@@ -525,7 +530,7 @@ struct Impl {
       c->tape.push_back(s);
     }
     for (int i = 0; i < 2 && K > 1; ++i)
-      if (!c->tape_f[i].ptr && (rc = dev_alloc(c, c->tape_f[i], gpf::Lat<D>::Q * cs))) return rc;
+      if (!c->tape_f[i].ptr && (rc = dev_alloc(c, c->tape_f[i], Q * cs))) return rc;
     gpf::KP<R> k = make_kp<R>(c);
     // lam^N = (seed, 0, 0, 0)
     StateBuf* li = &c->lam[0];
@@ -536,7 +541,7 @@ struct Impl {
                        c->stream, static_cast<const double*>(c->scratch.ptr), P(li->phi), N * c->cells);
     fill(c, li->mu, NC * c->cells);
     fill(c, li->u, D * c->cells);
-    fill(c, li->f, gpf::Lat<D>::Q * c->cells);
+    fill(c, li->f, Q * c->cells);
     hipLaunchKernelGGL((gpf::k_fill<double>), dim3(1), dim3(gpf::NG), 0, c->stream,
                        static_cast<double*>(c->t_acc.ptr), (int64_t)gpf::NG, 0.0);
     // per-block running sums of the parameter derivatives over the sweep
@@ -588,7 +593,7 @@ struct Impl {
       case GPF_PHI: src = P(l.phi); cnt = N * c->cells; break;
       case GPF_MU: src = P(l.mu); cnt = NC * c->cells; break;
       case GPF_U: src = P(l.u); cnt = D * c->cells; break;
-      case GPF_F: src = P(l.f); cnt = gpf::Lat<D>::Q * c->cells; break;
+      case GPF_F: src = P(l.f); cnt = Q * c->cells; break;
       default: return fail(c, GPF_ERR_ARG, "field %d has no adjoint", field);
     }
     hipLaunchKernelGGL((gpf::k_to_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, src,
@@ -604,20 +609,20 @@ struct Impl {
   }
 };
 
-template <int D, int N, class R>
+template <int D, int Q, int N, class R>
 const Ops* pick_nc(int nc) {
-  return nc == 1 ? Impl<D, N, 1, R>::ops() : Impl<D, N, 2, R>::ops();
+  return nc == 1 ? Impl<D, Q, N, 1, R>::ops() : Impl<D, Q, N, 2, R>::ops();
 }
-template <int D, class R>
+template <int D, int Q, class R>
 const Ops* pick_n(int N, int nc) {
-  return N == 2 ? pick_nc<D, 2, R>(nc) : pick_nc<D, 3, R>(nc);
+  return N == 2 ? pick_nc<D, Q, 2, R>(nc) : pick_nc<D, Q, 3, R>(nc);
 }
 template <class R>
-const Ops* pick_d(int dim, int N, int nc) {
-  return dim == 2 ? pick_n<2, R>(N, nc) : pick_n<3, R>(N, nc);
+const Ops* pick_d(int Q, int N, int nc) {
+  return Q == 9 ? pick_n<2, 9, R>(N, nc) : (Q == 19 ? pick_n<3, 19, R>(N, nc) : pick_n<3, 27, R>(N, nc));
 }
-const Ops* pick(int dim, int N, int nc, int prec) {
-  return prec == GPF_FP64 ? pick_d<double>(dim, N, nc) : pick_d<float>(dim, N, nc);
+const Ops* pick(int Q, int N, int nc, int prec) {
+  return prec == GPF_FP64 ? pick_d<double>(Q, N, nc) : pick_d<float>(Q, N, nc);
 }
 
 // ---------------------------------------------------------------------------
@@ -625,8 +630,9 @@ const Ops* pick(int dim, int N, int nc, int prec) {
 // ---------------------------------------------------------------------------
 int validate(gpf_ctx* c, const gpf_grid* g, int N, int K, const gpf_params* p) {
   if (g->dim != 2 && g->dim != 3) return fail(c, GPF_ERR_UNSUPPORTED, "dim must be 2 or 3, got %d", g->dim);
-  if ((g->dim == 2 && p->lattice != GPF_D2Q9) || (g->dim == 3 && p->lattice != GPF_D3Q19))
-    return fail(c, GPF_ERR_PARAM, "lattice %d does not match dim %d (D2Q9 in 2D, D3Q19 in 3D)",
+  if ((g->dim == 2 && p->lattice != GPF_D2Q9) ||
+      (g->dim == 3 && p->lattice != GPF_D3Q19 && p->lattice != GPF_D3Q27))
+    return fail(c, GPF_ERR_PARAM, "lattice %d does not match dim %d (D2Q9 in 2D, D3Q19 or D3Q27 in 3D)",
                 p->lattice, g->dim);
   if (N < 2 || N > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_phases must be 2 or 3, got %d", N);
   if (K < 2 || K > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_components must be 2 or 3, got %d", K);
@@ -735,7 +741,7 @@ int init_state(gpf_ctx* c, uint64_t seed) {
     for (int i = 0; i < c->nc; ++i)
       mu[(size_t)i * cells + P] = p.mu_inf[i] + p.noise_sigma * gauss(seed, (uint64_t)P * c->nc + i);
     for (int k = 0; k < c->Q; ++k)
-      f[(size_t)k * cells + P] = ((c->dim == 2) ? gpf::Lat<2>::w(k) : gpf::Lat<3>::w(k)) * p.rho0;
+      f[(size_t)k * cells + P] = lattice_w(c->Q, k) * p.rho0;
   }
   int rc;
   if ((rc = write_host(c, GPF_PHI, phi.data(), phi.size()))) return rc;
@@ -856,11 +862,11 @@ int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_co
   c->dim = grid->dim;
   c->N = n_phases;
   c->nc = n_components - 1;
-  c->Q = (c->dim == 2) ? 9 : 19;
+  c->Q = (c->dim == 2) ? 9 : (params->lattice == GPF_D3Q27 ? 27 : 19);
   for (int a = 0; a < 3; ++a) c->n[a] = (a < c->dim) ? grid->n[a] : 1;
   c->cells = c->n[0] * c->n[1] * c->n[2];
   c->esize = (params->precision == GPF_FP64) ? 8 : 4;
-  c->ops = pick(c->dim, c->N, c->nc, params->precision);
+  c->ops = pick(c->Q, c->N, c->nc, params->precision);
   const size_t cs = (size_t)c->cells * c->esize;
   for (int s = 0; s < 2 && !rc; ++s) {
     if (!rc) rc = dev_alloc(c, c->phi[s], c->N * cs);

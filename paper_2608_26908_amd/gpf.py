@@ -121,7 +121,7 @@ def make_grid(cfg):
 
 def make_params(cfg, precision):
     p = ParamsC()
-    p.lattice = 0 if cfg["dim"] == 2 else 1
+    p.lattice = 0 if cfg["dim"] == 2 else (2 if cfg.get("lattice") == "D3Q27" else 1)
     p.precision = PRECISION[precision]
     p.potential = {"obstacle": 0, "well": 1}[cfg.get("potential", "obstacle")]
     for k in ("dt", "eps", "tau_pf", "T_E", "T_iso", "G", "V", "y0", "tau_lb", "rho0",
@@ -169,7 +169,7 @@ class Sim:
         self.precision = precision or cfg.get("precision", "fp64")
         self.dim, self.N, self.nc = cfg["dim"], cfg["N"], cfg["nc"]
         self.n = tuple(int(v) for v in cfg["n"][: self.dim])
-        self.Q = 9 if self.dim == 2 else 19
+        self.Q = 9 if self.dim == 2 else (27 if self.cfg.get("lattice") == "D3Q27" else 19)
         self.cells = int(np.prod(self.n))
         self._grid = make_grid(self.cfg)
         self._params = make_params(self.cfg, self.precision)

@@ -73,6 +73,7 @@ def _try_init(gpf, cfg, N=None, K=None, **pk):
     (dict(dt=0.0), -2, "dt"),
     (dict(dt=0.5), -2, "bound"),
     (dict(lattice=1), -2, "lattice"),
+    (dict(lattice=2), -2, "lattice"),
     (dict(grav_axis=2), -2, "axis"),
     (dict(grav_sign=0), -2, "grav_sign"),
     (dict(W0=0.0), -2, "W0"),
