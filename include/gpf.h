@@ -121,6 +121,13 @@ typedef struct {
   double init_center[3], init_radius; /* seed centre (cell units, cell i at coordinate i), radius */
   double lam_width, lam_height;       /* lamella width along x, solid height along pull_axis */
   double mu_inf[2], noise_sigma;      /* mu^0_i = mu_inf_i + sigma z(seed, cell, i) */
+  int64_t frame_every;    /* moving frame of Case 2 (Sec. 3): every so many steps (0: off) the
+                             front -- the largest pull-axis index of a cell with phi_liq <= 1/2 --
+                             is found; if it lies beyond frame_front, every field moves down the
+                             pull axis by the excess, the new far planes repeat the last one and
+                             the frame origin (gpf_frame_offset) grows by it.  Needs walls on the
+                             pull axis; each check synchronises. */
+  int64_t frame_front;    /* pull-axis index the front is kept at, 0 <= frame_front < n[pull_axis] */
   int64_t health_every;   /* > 0: check NaN/Inf and rho <= 0 every so many steps and at the
                              end of each gpf_step call (the call then synchronises); 0: never */
   void* (*dev_alloc)(size_t bytes, void* user); /* NULL: hipMalloc; else e.g. torch's caching allocator */
@@ -206,7 +213,8 @@ int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
  * accumulated in FP64 in a fixed order; the adjoint fields have the
  * context's precision.  Synchronises.  Errors: GPF_ERR_STATE (nothing
  * recorded), GPF_ERR_ARG (count, unknown name, more than 6 names),
- * GPF_ERR_UNSUPPORTED (shrinkage force on: eta != 0), GPF_ERR_NOMEM.
+ * GPF_ERR_UNSUPPORTED (shrinkage force on: eta != 0, or a moving frame),
+ * GPF_ERR_NOMEM.
  *
  * gpf_adjoint_state: after gpf_adjoint, dL/d(initial recorded state) for
  * GPF_PHI, GPF_MU, GPF_U (velocity of the step before) or GPF_F (the
@@ -220,6 +228,11 @@ int gpf_adjoint_state(gpf_ctx* ctx, int32_t field, double* host_dst, size_t coun
  * setter is for resuming a checkpoint; n >= 0. */
 int64_t gpf_step_index(const gpf_ctx* ctx);
 int gpf_set_step_index(gpf_ctx* ctx, int64_t n);
+/* Cells the moving frame has shifted the fields along the pull axis so far
+ * (laboratory coordinate = grid index + offset; the pulled temperature uses
+ * it).  The setter is for resuming a checkpoint; offset >= 0. */
+int64_t gpf_frame_offset(const gpf_ctx* ctx);
+int gpf_set_frame_offset(gpf_ctx* ctx, int64_t offset);
 const char* gpf_last_error(const gpf_ctx* ctx);
 const char* gpf_status_string(int status);
 void gpf_destroy(gpf_ctx* ctx);

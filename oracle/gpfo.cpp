@@ -116,6 +116,7 @@ struct Par {
   long n[3];
   S dx, dt, eps, tau_pf, gamma[3][3], delta[3][3], chi[2][2], c0[3][2], dS[3], T_E, T_iso,
       D[3][2], G, V, y0, tau_lb, rho0, gbeta[2], c_ref[2], h_drag, W0, lid_u, eta[3];
+  long frame_every, frame_front;
 };
 
 template <class S>
@@ -165,6 +166,8 @@ Par<S> lift(const gpfo_params& p) {
   q.W0 = p.W0;
   q.lid_u = p.lid_u;
   for (int a = 0; a < 3; ++a) q.eta[a] = p.eta[a];
+  q.frame_every = (long)p.frame_every;
+  q.frame_front = (long)p.frame_front;
   return q;
 }
 
@@ -352,6 +355,7 @@ template <class S>
 struct State {
   std::vector<S> phi, mu, f, u; /* [N][cells], [nc][cells], [Q][cells], [dim][cells] */
   long step;
+  long shift = 0;               /* moving frame: cells shifted so far along the pull axis */
 };
 
 }  // namespace
@@ -367,11 +371,13 @@ namespace {
 
 /* ---------------- S0: temperature ------------------------------------------ */
 /* Frozen temperature pulled at V cells per step (Case 2/3 setting):
- * T = T_E + G (x_pull - y0 - V n); isothermal runs (G = 0) use T_iso. */
+ * T = T_E + G (x_pull + shift - y0 - V n), x_pull + shift the laboratory
+ * coordinate when a moving frame has shifted the fields by `shift` cells;
+ * isothermal runs (G = 0) use T_iso. */
 template <class S>
-S temperature(const Par<S>& p, const long* x, long nstep) {
+S temperature(const Par<S>& p, const long* x, long nstep, long shift) {
   if (re(p.G) == 0.0) return p.T_iso;
-  return p.T_E + p.G * (S((double)x[p.pull_axis]) - p.y0 - p.V * S((double)nstep));
+  return p.T_E + p.G * (S((double)(x[p.pull_axis] + shift)) - p.y0 - p.V * S((double)nstep));
 }
 
 /* ---------------- S1: active set -------------------------------------------- */
@@ -472,7 +478,7 @@ void pf_rhs(const Grid& g, const Par<S>& p, const State<S>& st, const long* x, l
   }
   S mu[2];
   for (int i = 0; i < p.nc; ++i) mu[i] = st.mu[i * nc_ + P];
-  S T = temperature(p, x, nstep);
+  S T = temperature(p, x, nstep, st.shift);
   S h[3], dh[9];
   interp_h(N, phiP, h, dh);
   S ps[3];
@@ -752,6 +758,56 @@ void step_once(const Grid& g, const Lattice& L, const Par<S>& p, State<S>& st) {
   st.step += 1;
 }
 
+/* ---------------- moving frame (Case 2: "a moving frame approach to follow
+ * the growth front"; the paper gives no details) ------------------------------
+ * Reading: after every frame_every steps the front is the largest pull-axis
+ * index of a cell whose liquid fraction is at most 1/2; when it lies beyond
+ * frame_front, every field (phi, mu, U, the stored populations) moves down the
+ * pull axis by d = front - frame_front cells, the d new planes at the far end
+ * repeat the last plane (zero gradient into the melt), the planes leaving at
+ * the near end are dropped, and the frame origin `shift` grows by d (it
+ * enters the frozen temperature). */
+template <class S>
+void frame_shift(const Grid& g, const Par<S>& p, State<S>& st) {
+  if (p.frame_every <= 0 || st.step % p.frame_every != 0) return;
+  const long cells = g.cells();
+  const int ax = p.pull_axis;
+  long front = -1;
+  for (long P = 0; P < cells; ++P) {
+    long x[3];
+    g.coords(P, x);
+    if (re(st.phi[(p.N - 1) * cells + P]) <= 0.5 && x[ax] > front) front = x[ax];
+  }
+  const long d = front - p.frame_front;
+  if (front < 0 || d <= 0) return;
+  auto move = [&](std::vector<S>& v) {
+    const long ncomp = (long)v.size() / cells;
+    std::vector<S> out(v.size());
+    for (long c = 0; c < ncomp; ++c)
+      for (long P = 0; P < cells; ++P) {
+        long x[3];
+        g.coords(P, x);
+        long y[3] = {x[0], x[1], x[2]};
+        y[ax] = std::min(x[ax] + d, g.n[ax] - 1);
+        out[c * cells + P] = v[c * cells + g.idx(y[0], y[1], y[2])];
+      }
+    v.swap(out);
+  };
+  move(st.phi);
+  move(st.mu);
+  move(st.u);
+  move(st.f);
+  st.shift += d;
+}
+
+template <class S>
+void advance(const Grid& g, const Lattice& L, const Par<S>& p, State<S>& st, int64_t nsteps) {
+  for (int64_t i = 0; i < nsteps; ++i) {
+    step_once(g, L, p, st);
+    frame_shift(g, p, st);
+  }
+}
+
 /* ---------------- initial state --------------------------------------------- */
 
 /* SplitMix64 (Steele, Lea and Flood 2014) used as a counter-based generator:
@@ -826,6 +882,7 @@ State<S> lift_state(const State<double>& s) {
   r.f.assign(s.f.begin(), s.f.end());
   r.u.assign(s.u.begin(), s.u.end());
   r.step = s.step;
+  r.shift = s.shift;
   return r;
 }
 
@@ -884,10 +941,11 @@ void gpfo_set_threads(int nthreads) {
 
 void gpfo_step(gpfo_sim* s, int64_t nsteps) {
   Par<double> p = lift<double>(s->prm);
-  for (int64_t i = 0; i < nsteps; ++i) step_once(s->g, s->L, p, s->st);
+  advance(s->g, s->L, p, s->st, nsteps);
 }
 
 int64_t gpfo_step_index(const gpfo_sim* s) { return s->st.step; }
+int64_t gpfo_frame_offset(const gpfo_sim* s) { return s->st.shift; }
 int64_t gpfo_cells(const gpfo_sim* s) { return s->g.cells(); }
 int32_t gpfo_Q(const gpfo_sim* s) { return s->L.Q; }
 
@@ -940,7 +998,7 @@ int gpfo_get(const gpfo_sim* s, int32_t field, double* dst) {
       for (long P = 0; P < cells; ++P) {
         long x[3];
         s->g.coords(P, x);
-        dst[P] = temperature(p, x, st.step);
+        dst[P] = temperature(p, x, st.step, st.shift);
       }
       return 0;
     case 7:
@@ -1049,7 +1107,7 @@ int gpfo_loss_grad_cs(const gpfo_sim* s, int64_t nsteps, const double* target, i
     default: return -1;
   }
   State<cplx> st = lift_state<cplx>(s->st);
-  for (int64_t i = 0; i < nsteps; ++i) step_once(s->g, s->L, p, st);
+  advance(s->g, s->L, p, st, nsteps);
   cplx L = 0;
   for (size_t j = 0; j < st.phi.size(); ++j) {
     cplx e = st.phi[j] - target[j];
@@ -1073,7 +1131,7 @@ int gpfo_tangent_cs(const gpfo_sim* s, int64_t nsteps, int32_t field, const doub
     default: return -1;
   }
   for (size_t j = 0; j < v->size(); ++j) (*v)[j] += cplx(0.0, h * dir[j]);
-  for (int64_t i = 0; i < nsteps; ++i) step_once(s->g, s->L, p, st);
+  advance(s->g, s->L, p, st, nsteps);
   std::vector<cplx>* o = nullptr;
   switch (out_field) {
     case 0: o = &st.phi; break;

@@ -71,6 +71,10 @@ typedef struct {
   double mu_inf[2], noise_sigma;
   double eta[3];          /* shrinkage: eta_a = (rho_a - rho_liq) / rho_liq (0: off) */
   int32_t lattice_q;      /* 3D lattice: 27 for D3Q27, anything else D3Q19 */
+  /* moving frame: after every frame_every steps (0: off), if the solid front
+   * (largest pull-axis index of a cell with phi_liq <= 1/2) lies beyond
+   * frame_front, every field is shifted down the pull axis by the excess */
+  int64_t frame_every, frame_front;
 } gpfo_params;
 
 typedef struct gpfo_sim gpfo_sim;
@@ -83,6 +87,8 @@ void gpfo_set_threads(int nthreads);
 /* Advance n coupled steps. */
 void gpfo_step(gpfo_sim* s, int64_t nsteps);
 int64_t gpfo_step_index(const gpfo_sim* s);
+/* cells the moving frame has shifted so far (the frame origin along the pull axis) */
+int64_t gpfo_frame_offset(const gpfo_sim* s);
 int64_t gpfo_cells(const gpfo_sim* s);
 int32_t gpfo_Q(const gpfo_sim* s);
 

@@ -47,7 +47,8 @@ class _Params(ctypes.Structure):
         ("init_radius", ctypes.c_double), ("lam_width", ctypes.c_double),
         ("lam_height", ctypes.c_double), ("mu_inf", ctypes.c_double * 2),
         ("noise_sigma", ctypes.c_double), ("eta", ctypes.c_double * 3),
-        ("lattice_q", ctypes.c_int32),
+        ("lattice_q", ctypes.c_int32), ("frame_every", ctypes.c_int64),
+        ("frame_front", ctypes.c_int64),
     ]
 
 
@@ -71,6 +72,8 @@ def lib():
         L.gpfo_step.argtypes = [vp, i64]
         L.gpfo_step_index.restype = i64
         L.gpfo_step_index.argtypes = [vp]
+        L.gpfo_frame_offset.restype = i64
+        L.gpfo_frame_offset.argtypes = [vp]
         L.gpfo_cells.restype = i64
         L.gpfo_cells.argtypes = [vp]
         L.gpfo_Q.restype = i32
@@ -147,6 +150,8 @@ def make_params(cfg):
     _fill(p.mu_inf, cfg["mu_inf"], (2,))
     _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]), (3,))
     p.lattice_q = 27 if cfg.get("lattice") == "D3Q27" else 0
+    p.frame_every = int(cfg.get("frame_every", 0))
+    p.frame_front = int(cfg.get("frame_front", 0))
     return p
 
 
@@ -175,6 +180,10 @@ class OracleSim:
     @property
     def step_index(self):
         return lib().gpfo_step_index(self._h)
+
+    @property
+    def frame_offset(self):
+        return lib().gpfo_frame_offset(self._h)
 
     @property
     def shape(self):

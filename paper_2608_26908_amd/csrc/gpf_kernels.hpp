@@ -712,6 +712,37 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
 // 1D grid.
 // ---------------------------------------------------------------------------
 
+// Moving frame (Case 2 follows the growth front with a moving frame; the
+// paper gives no details, the reading is stated with the host code).
+// k_front: the largest pull-axis index of a cell whose liquid fraction is at
+// most 1/2 (-1 if none), max-reduced over each wave, then one atomic per wave.
+template <int N, class R>
+__global__ void __launch_bounds__(256) k_front(KP<R> p, const R* __restrict__ phi, int* __restrict__ front) {
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int v = -1;
+  if (P < p.cells && phi[(N - 1) * p.cells + P] <= R(0.5)) {
+    const int64_t c = (p.pull_axis == 0) ? P % p.n[0]
+                      : (p.pull_axis == 1) ? (P / p.sy) % p.n[1] : P / p.sz;
+    v = (int)c;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0 && v >= 0) atomicMax(front, v);
+}
+
+// k_shift: out = in moved down an axis by d cells (index stride `stride`,
+// extent n_ax); the last d planes repeat the last plane of `in`.
+template <class R>
+__global__ void k_shift(const R* __restrict__ in, R* __restrict__ out, int64_t count, int64_t cells,
+                        int64_t stride, int64_t n_ax, int64_t d) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t P = i % cells;
+  const int64_t c = (P / stride) % n_ax;
+  const int64_t src = min(c + d, n_ax - 1);
+  out[i] = in[i + (src - c) * stride];
+}
+
 // f^n_k(P) = stored f*_k(P - c_k) (+ bounce-back), plus w_k rho0: the full f.
 template <int D, int Q, class R>
 __global__ void k_gather_f(KP<R> p, const R* __restrict__ fin, double* __restrict__ out) {
@@ -725,15 +756,23 @@ __global__ void k_gather_f(KP<R> p, const R* __restrict__ fin, double* __restric
     out[k * p.cells + P] = (double)pull_f<D, Q, R>(p, fin, x, y, z, P, k) + L::w(k) * (double)p.rho0;
 }
 
-// inverse of k_gather_f: the stored pre-streaming f* that streams to f^n
+// inverse of k_gather_f: the stored pre-streaming f* that streams to f^n.
+// With d > 0 it inverts the pull of f^n moved down axis `ax` by d cells (the
+// moving frame): every read of f^n at coordinate c along ax reads c + d,
+// clamped to the last plane.
 template <int D, int Q, class R>
-__global__ void k_scatter_f(KP<R> p, const double* __restrict__ fn, R* __restrict__ fst) {
+__global__ void k_scatter_f(KP<R> p, const double* __restrict__ fn, R* __restrict__ fst, int ax, int d) {
   using L = Lat<Q>;
   const int64_t Qc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (Qc >= p.cells) return;
   const int x = (int)(Qc % p.n[0]);
   const int y = (int)((Qc / p.sy) % p.n[1]);
   const int z = (int)(Qc / p.sz);
+  auto at = [&](int c0, int c1, int c2) -> int64_t {
+    int c[3] = {c0, c1, c2};
+    c[ax] = min(c[ax] + d, p.n[ax] - 1);
+    return (int64_t)c[2] * p.sz + (int64_t)c[1] * p.sy + c[0];
+  };
   for (int k = 0; k < L::Q; ++k) {
     int dst[3] = {x + L::c(k, 0), y + L::c(k, 1), z + L::c(k, 2)};
     bool in = true;
@@ -746,10 +785,10 @@ __global__ void k_scatter_f(KP<R> p, const double* __restrict__ fn, R* __restric
       }
     double val;
     if (in) {
-      val = fn[k * p.cells + (int64_t)dst[2] * p.sz + (int64_t)dst[1] * p.sy + dst[0]] - L::w(k) * (double)p.rho0;
+      val = fn[k * p.cells + at(dst[0], dst[1], dst[2])] - L::w(k) * (double)p.rho0;
     } else {
       const int kb = L::opp(k);
-      val = fn[kb * p.cells + Qc] - L::w(kb) * (double)p.rho0;
+      val = fn[kb * p.cells + at(x, y, z)] - L::w(kb) * (double)p.rho0;
       if (L::c(kb, 1) < 0 && !p.per[1] && y - L::c(kb, 1) >= p.n[1])
         val -= 6.0 * L::w(kb) * (double)p.rho0 * L::c(kb, 0) * (double)p.lid_u;
     }

@@ -57,6 +57,8 @@ struct gpf_ctx {
   DevBuf partial;   // reduction partials
   DevBuf redout;    // final reduction values
   DevBuf badstep;   // health: smallest failing step
+  DevBuf frontbuf;  // moving frame: front position found on the device
+  int64_t frame_off = 0;  // moving frame: cells shifted so far along the pull axis
   const Ops* ops = nullptr;
   std::string err;
   // adjoint: checkpoints every rec_every steps from step rec_start
@@ -196,13 +198,17 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
 }
 
 // the pulled temperature's moving origin y0 + V n
-double tshift(const gpf_ctx* c, int64_t step) { return c->prm.y0 + c->prm.V * (double)step; }
+// T - T_E = G (x_pull - tshift): x_pull + frame_off is the laboratory coordinate
+double tshift(const gpf_ctx* c, int64_t step) {
+  return c->prm.y0 + c->prm.V * (double)step - (double)c->frame_off;
+}
 
 // ---------------------------------------------------------------------------
 // per-instance launchers
 // ---------------------------------------------------------------------------
 struct Ops {
   int (*step)(gpf_ctx*, int64_t, double*, int);
+  int (*frame)(gpf_ctx*);
   int (*read)(gpf_ctx*, int, double*);  // to scratch (device FP64), returns components
   int (*write)(gpf_ctx*, int);          // from scratch
   int (*reduce)(gpf_ctx*, int, double*);
@@ -275,6 +281,48 @@ struct Impl {
     if (ev) (void)hipEventRecord(ev[2], c->stream);
   }
 
+  // Moving frame.  Reading (the paper names the approach only): every
+  // frame_every steps the front is the largest pull-axis index of a cell with
+  // liquid fraction <= 1/2; beyond frame_front, every field of the state
+  // (phi, mu, U, the streamed populations f^n) moves down the pull axis by the
+  // excess d into the other buffer set, the d new far planes repeat the last
+  // plane (zero gradient into the melt) and the frame origin grows by d.
+  static int frame(gpf_ctx* c) {
+    gpf::KP<R> k = make_kp<R>(c);
+    int* fb = static_cast<int*>(c->frontbuf.ptr);
+    hipLaunchKernelGGL((gpf::k_fill<int>), dim3(1), dim3(64), 0, c->stream, fb, (int64_t)1, -1);
+    hipLaunchKernelGGL((gpf::k_front<N, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0, c->stream, k,
+                       P(c->phi[c->cur]), fb);
+    HIP_OR_FAIL(c, hipGetLastError());
+    int front = -1;
+    HIP_OR_FAIL(c, hipMemcpyAsync(&front, fb, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    const int64_t d = (int64_t)front - c->prm.frame_front;
+    if (front < 0 || d <= 0) return GPF_OK;
+    const int ax = c->prm.pull_axis;
+    const int64_t stride = ax == 0 ? 1 : (ax == 1 ? c->n[0] : c->n[0] * c->n[1]);
+    const int s = c->cur, t = 1 - c->cur;
+    auto mv = [&](DevBuf& in, DevBuf& out, int ncomp) {
+      const int64_t count = (int64_t)ncomp * c->cells;
+      hipLaunchKernelGGL((gpf::k_shift<R>), dim3(lin_blocks(count, 256)), dim3(256), 0, c->stream, P(in), P(out),
+                         count, c->cells, stride, c->n[ax], d);
+    };
+    mv(c->phi[s], c->phi[t], N);
+    mv(c->mu[s], c->mu[t], NC);
+    mv(c->u[s], c->u[t], D);
+    // the populations move as the streamed f^n of the state: pull them into
+    // FP64 staging, then store the f* whose pull gives f^n moved by d
+    double* fs = static_cast<double*>(c->scratch.ptr);
+    hipLaunchKernelGGL((gpf::k_gather_f<D, Q, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0, c->stream, k,
+                       P(c->f[s]), fs);
+    hipLaunchKernelGGL((gpf::k_scatter_f<D, Q, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0, c->stream, k,
+                       fs, P(c->f[t]), ax, (int)d);
+    HIP_OR_FAIL(c, hipGetLastError());
+    c->cur = t;
+    c->frame_off += d;
+    return GPF_OK;
+  }
+
   static int step(gpf_ctx* c, int64_t nsteps, double* kernel_ms, int nk) {
     gpf::KP<R> k = make_kp<R>(c);
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -298,6 +346,10 @@ struct Impl {
       }
       c->cur = t;
       c->step += 1;
+      if (c->prm.frame_every > 0 && c->step % c->prm.frame_every == 0) {
+        int rc = frame(c);
+        if (rc) return rc;
+      }
       if (H > 0 && (c->step % H == 0 || it == nsteps - 1)) {
         int rc = health(c);
         if (rc) return rc;
@@ -406,7 +458,7 @@ struct Impl {
                          P(c->f[s]), cnt);
     } else if (field == GPF_F) {
       hipLaunchKernelGGL((gpf::k_scatter_f<D, Q, R>), dim3(lin_blocks(c->cells, 256)), dim3(256), 0,
-                         c->stream, k, in, P(c->f[s]));
+                         c->stream, k, in, P(c->f[s]), 0, 0);
     } else if (field == GPF_MU) {
       const int64_t cnt = NC * c->cells;
       hipLaunchKernelGGL((gpf::k_mu_from_double<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream, in,
@@ -604,7 +656,7 @@ struct Impl {
   }
 
   static const Ops* ops() {
-    static const Ops o = {&step, &read, &write, &reduce, &read_native, &adjoint, &copy_state, &lam_read};
+    static const Ops o = {&step, &frame, &read, &write, &reduce, &read_native, &adjoint, &copy_state, &lam_read};
     return &o;
   }
 };
@@ -638,6 +690,15 @@ int validate(gpf_ctx* c, const gpf_grid* g, int N, int K, const gpf_params* p) {
   if (K < 2 || K > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_components must be 2 or 3, got %d", K);
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->eta[a])) return fail(c, GPF_ERR_PARAM, "eta[%d] is not finite", a);
+  if (p->frame_every < 0) return fail(c, GPF_ERR_PARAM, "frame_every must be >= 0");
+  if (p->frame_every > 0) {
+    const int ax = p->pull_axis;
+    if (ax < 0 || ax >= g->dim || (g->periodic_mask >> ax) & 1u)
+      return fail(c, GPF_ERR_PARAM, "the moving frame needs walls on the pull axis");
+    if (p->frame_front < 0 || p->frame_front >= g->n[ax])
+      return fail(c, GPF_ERR_PARAM, "frame_front %lld outside [0, %lld)", (long long)p->frame_front,
+                  (long long)g->n[ax]);
+  }
   if (p->precision != GPF_FP64 && p->precision != GPF_FP32)
     return fail(c, GPF_ERR_ARG, "unknown precision %d", p->precision);
   if (p->potential != GPF_OBSTACLE && p->potential != GPF_WELL)
@@ -789,6 +850,7 @@ void free_all(gpf_ctx* c) {
   dev_release(c, c->partial);
   dev_release(c, c->redout);
   dev_release(c, c->badstep);
+  dev_release(c, c->frontbuf);
   auto rel = [&](StateBuf& s) {
     dev_release(c, s.phi);
     dev_release(c, s.mu);
@@ -878,6 +940,7 @@ int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_co
   if (!rc) rc = dev_alloc(c, c->partial, 2048 * 2 * sizeof(double));
   if (!rc) rc = dev_alloc(c, c->redout, 4 * sizeof(double));
   if (!rc) rc = dev_alloc(c, c->badstep, sizeof(unsigned long long));
+  if (!rc) rc = dev_alloc(c, c->frontbuf, sizeof(int));
   if (!rc) {
     hipError_t e = hipMemsetAsync(c->badstep.ptr, 0xff, sizeof(unsigned long long), c->stream);
     if (e != hipSuccess) rc = fail(c, GPF_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
@@ -1037,6 +1100,8 @@ int gpf_adjoint(gpf_ctx* c, const double* dL_dphi, size_t count, const char* con
   for (int a = 0; a < 3; ++a)
     if (c->prm.eta[a] != 0.0)
       return fail(c, GPF_ERR_UNSUPPORTED, "the adjoint does not include the shrinkage force (eta != 0)");
+  if (c->prm.frame_every > 0)
+    return fail(c, GPF_ERR_UNSUPPORTED, "the adjoint does not include the moving frame (frame_every > 0)");
   int slots[gpf::NG];
   for (int i = 0; i < n_names; ++i) {
     slots[i] = names[i] ? grad_slot(names[i]) : -1;
@@ -1066,6 +1131,15 @@ int gpf_set_step_index(gpf_ctx* c, int64_t n) {
   if (!c) return GPF_ERR_ARG;
   if (n < 0) return fail(c, GPF_ERR_ARG, "negative step index");
   c->step = n;
+  return GPF_OK;
+}
+
+int64_t gpf_frame_offset(const gpf_ctx* c) { return c ? c->frame_off : -1; }
+
+int gpf_set_frame_offset(gpf_ctx* c, int64_t offset) {
+  if (!c) return GPF_ERR_ARG;
+  if (offset < 0) return fail(c, GPF_ERR_ARG, "negative frame offset");
+  c->frame_off = offset;
   return GPF_OK;
 }
 

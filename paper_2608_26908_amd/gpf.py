@@ -56,7 +56,8 @@ class ParamsC(ctypes.Structure):
         ("init_kind", ctypes.c_int32), ("init_center", ctypes.c_double * 3),
         ("init_radius", ctypes.c_double), ("lam_width", ctypes.c_double),
         ("lam_height", ctypes.c_double), ("mu_inf", ctypes.c_double * 2),
-        ("noise_sigma", ctypes.c_double), ("health_every", ctypes.c_int64),
+        ("noise_sigma", ctypes.c_double), ("frame_every", ctypes.c_int64),
+        ("frame_front", ctypes.c_int64), ("health_every", ctypes.c_int64),
         ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p),
     ]
 
@@ -86,6 +87,9 @@ def lib():
         L.gpf_set_step_index.argtypes = [vp, i64]
         L.gpf_step_index.restype = i64
         L.gpf_step_index.argtypes = [vp]
+        L.gpf_frame_offset.restype = i64
+        L.gpf_frame_offset.argtypes = [vp]
+        L.gpf_set_frame_offset.argtypes = [vp, i64]
         L.gpf_last_error.restype = ctypes.c_char_p
         L.gpf_last_error.argtypes = [vp]
         L.gpf_status_string.restype = ctypes.c_char_p
@@ -136,6 +140,8 @@ def make_params(cfg, precision):
     _fill(p.init_center, cfg.get("init_center", [0.0, 0.0, 0.0]))
     _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]))
     p.health_every = int(cfg.get("health_every", 0))
+    p.frame_every = int(cfg.get("frame_every", 0))
+    p.frame_front = int(cfg.get("frame_front", 0))
     return p
 
 
@@ -226,15 +232,25 @@ class Sim:
     def step_index(self, n):
         self._check(lib().gpf_set_step_index(self._h, int(n)))
 
+    @property
+    def frame_offset(self):
+        return lib().gpf_frame_offset(self._h)
+
+    @frame_offset.setter
+    def frame_offset(self, s):
+        self._check(lib().gpf_set_frame_offset(self._h, int(s)))
+
     def checkpoint(self):
-        """exact copy of the state (bitwise resumable)"""
-        return {k: self.read(k) for k in ("phi", "mu", "u", "fpost")}, self.step_index
+        """exact copy of the state (bitwise resumable): fields, step index,
+        moving-frame offset"""
+        return {k: self.read(k) for k in ("phi", "mu", "u", "fpost")}, self.step_index, self.frame_offset
 
     def restore(self, ckpt):
-        state, n = ckpt
+        state, n, off = ckpt
         for k, v in state.items():
             self.write(k, v)
         self.step_index = n
+        self.frame_offset = off
 
     def step(self, n=1):
         self._check(lib().gpf_step(self._h, int(n)))

@@ -78,6 +78,8 @@ def _try_init(gpf, cfg, N=None, K=None, **pk):
     (dict(grav_sign=0), -2, "grav_sign"),
     (dict(W0=0.0), -2, "W0"),
     (dict(precision=7), -1, "precision"),
+    (dict(frame_every=-1), -2, "frame_every"),
+    (dict(frame_every=10, frame_front=500), -2, "frame_front"),
 ])
 def test_init_rejects_bad_parameters_without_device(gpf, change, code, word):
     from paper_2608_26908_amd.workloads import workload
@@ -102,3 +104,10 @@ def test_binding_fails_loudly_without_gpu(gpf):
     from paper_2608_26908_amd.workloads import workload
     with pytest.raises(RuntimeError):
         gpf.Sim(workload("dendrite2d"))
+
+
+def test_moving_frame_needs_walls_on_the_pull_axis(gpf):
+    from paper_2608_26908_amd.workloads import workload
+    cfg = workload("eutectic2d", periodic=[1, 1])
+    rc, msg, h = _try_init(gpf, cfg, frame_every=10, frame_front=20)
+    assert rc == -2 and "walls" in msg and not h.value

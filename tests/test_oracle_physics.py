@@ -457,3 +457,29 @@ def test_shrinkage_response_is_linear_in_eta(oracle):
     d1, d3 = out[0.1] - out[0.0], out[0.3] - out[0.0]
     assert np.abs(d1).max() > 1e-4
     assert np.abs(d3 - 3 * d1).max() <= 1e-12 * np.abs(d3).max()
+
+
+def test_moving_frame_is_a_translation(oracle):
+    """The moving frame (Case 2) only relabels cells: away from the planes it
+    adds and drops, a run with the frame equals the run without it, read
+    S cells further along the pull axis (S the frame offset), bit for bit —
+    the pulled temperature uses laboratory coordinates in both."""
+    from paper_2608_26908_amd.workloads import scaled
+    cfg = scaled("eutectic2d", [48, 96], lam_height=30.0, y0=30.0)
+    on = oracle.OracleSim(dict(cfg, frame_every=40, frame_front=24))
+    off = oracle.OracleSim(cfg)
+    on.step(40)
+    off.step(40)
+    S = on.frame_offset
+    assert S > 0
+    # the front (last plane with liquid fraction <= 1/2) now sits at frame_front
+    solid_rows = np.where((on.get("phi")[2] <= 0.5).any(axis=1))[0]
+    assert solid_rows.max() == 24
+    on.step(12)
+    off.step(12)
+    assert on.frame_offset == S
+    lo, hi = 14, 96 - S - 14  # 12 steps carry a boundary's influence < 14 cells
+    for k in ("phi", "mu", "f", "u", "T"):
+        a, b = on.get(k), off.get(k)
+        assert np.array_equal(a[:, lo:hi, :] if a.ndim == 3 else a[lo:hi], b[:, lo + S:hi + S, :]
+                              if b.ndim == 3 else b[lo + S:hi + S]), k
