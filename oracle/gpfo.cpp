@@ -40,6 +40,7 @@ inline double re(double x) { return x; }
 inline double re(const cplx& z) { return z.real(); }
 
 const double PI = 3.14159265358979323846;
+constexpr int NP = 4; /* most phases (three solids and the liquid) */
 
 /* ---------------- lattices (Table LBM_Schemes; D3Q19 textbook) ------------- */
 
@@ -114,8 +115,8 @@ template <class S>
 struct Par {
   int dim, N, nc, potential, periodic[3], pull_axis, grav_axis, grav_sign;
   long n[3];
-  S dx, dt, eps, tau_pf, gamma[3][3], delta[3][3], chi[2][2], c0[3][2], dS[3], T_E, T_iso,
-      D[3][2], G, V, y0, tau_lb, rho0, gbeta[2], c_ref[2], h_drag, W0, lid_u, eta[3];
+  S dx, dt, eps, tau_pf, gamma[NP][NP], delta[NP][NP], chi[2][2], c0[NP][2], dS[NP], T_E, T_iso,
+      D[NP][2], G, V, y0, tau_lb, rho0, gbeta[2], c_ref[2], h_drag, W0, lid_u, eta[NP];
   long frame_every, frame_front;
 };
 
@@ -137,14 +138,14 @@ Par<S> lift(const gpfo_params& p) {
   q.dt = p.dt;
   q.eps = p.eps;
   q.tau_pf = p.tau_pf;
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
+  for (int a = 0; a < NP; ++a)
+    for (int b = 0; b < NP; ++b) {
       q.gamma[a][b] = p.gamma[a][b];
       q.delta[a][b] = p.delta[a][b];
     }
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) q.chi[i][j] = p.chi[i][j];
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < NP; ++a) {
     for (int i = 0; i < 2; ++i) {
       q.c0[a][i] = p.c0[a][i];
       q.D[a][i] = p.D[a][i];
@@ -165,7 +166,7 @@ Par<S> lift(const gpfo_params& p) {
   q.h_drag = p.h_drag;
   q.W0 = p.W0;
   q.lid_u = p.lid_u;
-  for (int a = 0; a < 3; ++a) q.eta[a] = p.eta[a];
+  for (int a = 0; a < NP; ++a) q.eta[a] = p.eta[a];
   q.frame_every = (long)p.frame_every;
   q.frame_front = (long)p.frame_front;
   return q;
@@ -221,8 +222,10 @@ void aniso_dAdq(int dim, const S* q, S gamma, S delta, S* out) {
 
 /* Interpolation functions h_a(phi) (the paper uses h without defining it):
  * N = 2: h_a = phi_a^2 (3 - 2 phi_a);
- * N = 3: h_a = phi_a^2 (3 - 2 phi_a) + 2 phi_a phi_b phi_g.
- * Both sum to 1 on the Gibbs simplex.  dh[b*N + a] = d h_b / d phi_a. */
+ * N = 3: h_a = phi_a^2 (3 - 2 phi_a) + 2 phi_a phi_b phi_g;
+ * N = 4: h_a = phi_a^2 (3 - 2 phi_a) + 2 phi_a sum_{b < g, both != a} phi_b phi_g.
+ * All sum to 1 on the Gibbs simplex (3 p2 - 2 p3 + 6 e3 = 1 when e1 = 1).
+ * dh[b*N + a] = d h_b / d phi_a. */
 template <class S>
 void interp_h(int N, const S* phi, S* h, S* dh) {
   for (int b = 0; b < N; ++b) {
@@ -230,16 +233,23 @@ void interp_h(int N, const S* phi, S* h, S* dh) {
     for (int a = 0; a < N; ++a) dh[b * N + a] = S(0.0);
     dh[b * N + b] = S(6.0) * phi[b] * (S(1.0) - phi[b]);
   }
-  if (N == 3) {
-    S prod = phi[0] * phi[1] * phi[2];
-    for (int b = 0; b < 3; ++b) {
-      h[b] += S(2.0) * prod;
-      for (int a = 0; a < 3; ++a) {
-        /* d(2 phi0 phi1 phi2)/d phi_a = 2 * product of the other two */
-        S other = S(1.0);
-        for (int g = 0; g < 3; ++g)
-          if (g != a) other *= phi[g];
-        dh[b * N + a] += S(2.0) * other;
+  if (N >= 3) {
+    /* + 2 phi_b e_b, e_b = sum over the pairs {g < k} of the other phases of
+     * phi_g phi_k (for N = 3 the single product of the other two) */
+    for (int b = 0; b < N; ++b) {
+      S e = S(0.0);
+      for (int g = 0; g < N; ++g)
+        for (int k = g + 1; k < N; ++k)
+          if (g != b && k != b) e += phi[g] * phi[k];
+      h[b] += S(2.0) * phi[b] * e;
+      dh[b * N + b] += S(2.0) * e;
+      for (int a = 0; a < N; ++a) {
+        if (a == b) continue;
+        /* d e_b / d phi_a = sum of the phases other than a and b */
+        S rest = S(0.0);
+        for (int g = 0; g < N; ++g)
+          if (g != a && g != b) rest += phi[g];
+        dh[b * N + a] += S(2.0) * phi[b] * rest;
       }
     }
   }
@@ -434,7 +444,7 @@ void pf_rhs(const Grid& g, const Par<S>& p, const State<S>& st, const long* x, l
   const int d = p.dim, N = p.N;
   const long nc_ = g.cells();
   const long P = g.idx(x[0], x[1], x[2]);
-  S div[3] = {0, 0, 0};
+  S div[NP] = {};
   for (int a = 0; a < d; ++a) {
     for (int s = -1; s <= 1; s += 2) {
       long xq = x[a] + s;
@@ -442,7 +452,7 @@ void pf_rhs(const Grid& g, const Par<S>& p, const State<S>& st, const long* x, l
       int oq[3] = {0, 0, 0};
       oq[a] = s;
       int o0[3] = {0, 0, 0};
-      S phif[3], grf[3][3];
+      S phif[NP], grf[NP][3];
       for (int b = 0; b < N; ++b) {
         S pP = st.phi[b * nc_ + P];
         S pQ = phi_at(g, st, b, x, oq[0], oq[1], oq[2]);
@@ -469,9 +479,9 @@ void pf_rhs(const Grid& g, const Par<S>& p, const State<S>& st, const long* x, l
     }
   }
   /* cell-centre term d a / d phi_a = sum_b dA_ab/dq . grad phi_b */
-  S gc[3][3];
+  S gc[NP][3];
   int o0[3] = {0, 0, 0};
-  S phiP[3];
+  S phiP[NP];
   for (int b = 0; b < N; ++b) {
     phiP[b] = st.phi[b * nc_ + P];
     for (int e = 0; e < d; ++e) gc[b][e] = grad_c(g, p, st, b, x, o0, e);
@@ -479,9 +489,9 @@ void pf_rhs(const Grid& g, const Par<S>& p, const State<S>& st, const long* x, l
   S mu[2];
   for (int i = 0; i < p.nc; ++i) mu[i] = st.mu[i * nc_ + P];
   S T = temperature(p, x, nstep, st.shift);
-  S h[3], dh[9];
+  S h[NP], dh[NP * NP];
   interp_h(N, phiP, h, dh);
-  S ps[3];
+  S ps[NP];
   for (int b = 0; b < N; ++b) ps[b] = psi(p, b, mu, T);
   for (int al = 0; al < N; ++al) {
     S cell = 0;
@@ -525,7 +535,7 @@ void mu_cell(const Grid& g, const Par<S>& p, const State<S>& st, const std::vect
   const int d = p.dim, N = p.N, nc = p.nc;
   const long cells = g.cells();
   auto cell_quant = [&](long j, S* M /*nc*nc*/, S* cstar /*nc*/) {
-    S ph[3] = {0, 0, 0}, h[3], dh[9];
+    S ph[NP] = {}, h[NP], dh[NP * NP];
     for (int a = 0; a < N; ++a) ph[a] = phin[a * cells + j];
     interp_h(N, ph, h, dh);
     S mu[2];
@@ -569,7 +579,7 @@ void mu_cell(const Grid& g, const Par<S>& p, const State<S>& st, const std::vect
       }
     }
   }
-  S ph0[3], ph1[3], h0[3], h1[3], dh[9], mu[2];
+  S ph0[NP], ph1[NP], h0[NP], h1[NP], dh[NP * NP], mu[2];
   for (int a = 0; a < N; ++a) {
     ph0[a] = st.phi[a * cells + P];
     ph1[a] = phin[a * cells + P];
@@ -690,11 +700,11 @@ void step_once(const Grid& g, const Lattice& L, const Par<S>& p, State<S>& st) {
       for (int a = 0; a < N; ++a) phin[a * cells + P] = st.phi[a * cells + P];
       continue;
     }
-    S R[3];
+    S R[NP];
     pf_rhs(g, p, st, x, st.step, R);
-    S v[3], w[3];
+    S v[NP], w[NP];
     int m = 0;
-    int which[3];
+    int which[NP];
     for (int a = 0; a < N; ++a)
       if ((A >> a) & 1u) {
         v[m] = st.phi[a * cells + P] + rate * R[a];
@@ -863,7 +873,9 @@ void init_state(gpfo_sim* S_, uint64_t seed) {
     } else if (p.init_kind == GPFO_INIT_LAMELLAE) {
       double s = ((double)x[p.pull_axis] - p.lam_height) * p.dx;
       sol = obstacle_profile(s, p.eps);
-      if (p.N == 3 && p.lam_width > 0) solid_phase = ((long)std::floor((double)x[0] / p.lam_width)) % 2;
+      /* the N - 1 solids take turns along x, lam_width cells each */
+      if (p.N >= 3 && p.lam_width > 0)
+        solid_phase = ((long)std::floor((double)x[0] / p.lam_width)) % (p.N - 1);
     }
     st.phi[(size_t)solid_phase * cells + P] = sol;
     st.phi[(size_t)(p.N - 1) * cells + P] = 1.0 - sol;
@@ -910,7 +922,7 @@ extern "C" {
 gpfo_sim* gpfo_create(const gpfo_params* p, uint64_t seed) {
   if (!p) return nullptr;
   if (p->dim != 2 && p->dim != 3) return nullptr;
-  if (p->N < 2 || p->N > 3 || p->nc < 1 || p->nc > 2) return nullptr;
+  if (p->N < 2 || p->N > NP || p->nc < 1 || p->nc > 2) return nullptr;
   gpfo_sim* s = new gpfo_sim;
   s->prm = *p;
   s->g.dim = p->dim;
@@ -982,7 +994,7 @@ int gpfo_get(const gpfo_sim* s, int32_t field, double* dst) {
     case 4: std::copy(st.u.begin(), st.u.end(), dst); return 0;
     case 5:
       for (long P = 0; P < cells; ++P) {
-        double ph[3], h[3], dh[9], mu[2];
+        double ph[NP], h[NP], dh[NP * NP], mu[2];
         for (int a = 0; a < p.N; ++a) ph[a] = st.phi[a * cells + P];
         for (int i = 0; i < p.nc; ++i) mu[i] = st.mu[i * cells + P];
         interp_h(p.N, ph, h, dh);
@@ -1095,8 +1107,8 @@ int gpfo_loss_grad_cs(const gpfo_sim* s, int64_t nsteps, const double* target, i
   const cplx ih(0.0, h);
   switch (which) {
     case GPFO_P_DELTA:
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < NP; ++a)
+        for (int b = 0; b < NP; ++b)
           if (s->prm.delta[a][b] != 0.0) p.delta[a][b] += ih;
       break;
     case GPFO_P_TAU: p.tau_pf += ih; break;

@@ -46,17 +46,17 @@ typedef struct {
   int32_t dim;            /* 2 or 3 */
   int64_t n[3];           /* cells per axis (n[2] = 1 in 2D) */
   int32_t periodic[3];    /* 1: periodic axis, 0: walls at both ends */
-  int32_t N;              /* phases, liquid is the last one (2 or 3) */
+  int32_t N;              /* phases, liquid is the last one (2, 3 or 4) */
   int32_t nc;             /* independent solutes K-1 (1 or 2) */
   int32_t potential;      /* GPFO_OBSTACLE (paper) or GPFO_WELL (test only) */
   double dx, dt, eps, tau_pf;
-  double gamma[3][3];     /* interface energies gamma_ab (symmetric) */
-  double delta[3][3];     /* cubic anisotropy strength per pair (symmetric) */
+  double gamma[4][4];     /* interface energies gamma_ab (symmetric) */
+  double delta[4][4];     /* cubic anisotropy strength per pair (symmetric) */
   double chi[2][2];       /* susceptibility dC/dmu, common to all phases (SPD) */
-  double c0[3][2];        /* C^a(mu) = c0[a] + chi mu */
-  double dS[3];           /* psi^a gets + dS[a] (T - T_E); liquid dS = 0 */
+  double c0[4][2];        /* C^a(mu) = c0[a] + chi mu */
+  double dS[4];           /* psi^a gets + dS[a] (T - T_E); liquid dS = 0 */
   double T_E, T_iso;
-  double D[3][2];         /* diffusivity per phase and solute */
+  double D[4][2];         /* diffusivity per phase and solute */
   double G, V, y0;        /* frozen gradient T = T_E + G (x_p - y0 - V n); G = 0: T = T_iso */
   int32_t pull_axis;
   double tau_lb, rho0;
@@ -69,7 +69,7 @@ typedef struct {
   double init_center[3], init_radius;
   double lam_width, lam_height;
   double mu_inf[2], noise_sigma;
-  double eta[3];          /* shrinkage: eta_a = (rho_a - rho_liq) / rho_liq (0: off) */
+  double eta[4];          /* shrinkage: eta_a = (rho_a - rho_liq) / rho_liq (0: off) */
   int32_t lattice_q;      /* 3D lattice: 27 for D3Q27, anything else D3Q19 */
   /* moving frame: after every frame_every steps (0: off), if the solid front
    * (largest pull-axis index of a cell with phi_liq <= 1/2) lies beyond

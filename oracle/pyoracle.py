@@ -33,10 +33,10 @@ class _Params(ctypes.Structure):
         ("N", ctypes.c_int32), ("nc", ctypes.c_int32), ("potential", ctypes.c_int32),
         ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("eps", ctypes.c_double),
         ("tau_pf", ctypes.c_double),
-        ("gamma", (ctypes.c_double * 3) * 3), ("delta", (ctypes.c_double * 3) * 3),
-        ("chi", (ctypes.c_double * 2) * 2), ("c0", (ctypes.c_double * 2) * 3),
-        ("dS", ctypes.c_double * 3), ("T_E", ctypes.c_double), ("T_iso", ctypes.c_double),
-        ("D", (ctypes.c_double * 2) * 3),
+        ("gamma", (ctypes.c_double * 4) * 4), ("delta", (ctypes.c_double * 4) * 4),
+        ("chi", (ctypes.c_double * 2) * 2), ("c0", (ctypes.c_double * 2) * 4),
+        ("dS", ctypes.c_double * 4), ("T_E", ctypes.c_double), ("T_iso", ctypes.c_double),
+        ("D", (ctypes.c_double * 2) * 4),
         ("G", ctypes.c_double), ("V", ctypes.c_double), ("y0", ctypes.c_double),
         ("pull_axis", ctypes.c_int32),
         ("tau_lb", ctypes.c_double), ("rho0", ctypes.c_double),
@@ -46,7 +46,7 @@ class _Params(ctypes.Structure):
         ("init_kind", ctypes.c_int32), ("init_center", ctypes.c_double * 3),
         ("init_radius", ctypes.c_double), ("lam_width", ctypes.c_double),
         ("lam_height", ctypes.c_double), ("mu_inf", ctypes.c_double * 2),
-        ("noise_sigma", ctypes.c_double), ("eta", ctypes.c_double * 3),
+        ("noise_sigma", ctypes.c_double), ("eta", ctypes.c_double * 4),
         ("lattice_q", ctypes.c_int32), ("frame_every", ctypes.c_int64),
         ("frame_front", ctypes.c_int64),
     ]
@@ -138,17 +138,17 @@ def make_params(cfg):
     p.grav_axis = cfg.get("grav_axis", 1)
     p.grav_sign = cfg.get("grav_sign", -1)
     p.init_kind = {"seed": 0, "lamellae": 1, "liquid": 2}[cfg.get("init", "seed")]
-    _fill(p.gamma, cfg["gamma"], (3, 3))
-    _fill(p.delta, cfg["delta"], (3, 3))
+    _fill(p.gamma, cfg["gamma"], (4, 4))
+    _fill(p.delta, cfg["delta"], (4, 4))
     _fill(p.chi, cfg["chi"], (2, 2))
-    _fill(p.c0, cfg["c0"], (3, 2))
-    _fill(p.dS, cfg["dS"], (3,))
-    _fill(p.D, cfg["D"], (3, 2))
+    _fill(p.c0, cfg["c0"], (4, 2))
+    _fill(p.dS, cfg["dS"], (4,))
+    _fill(p.D, cfg["D"], (4, 2))
     _fill(p.gbeta, cfg["gbeta"], (2,))
     _fill(p.c_ref, cfg["c_ref"], (2,))
     _fill(p.init_center, cfg.get("init_center", [0, 0, 0]), (3,))
     _fill(p.mu_inf, cfg["mu_inf"], (2,))
-    _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]), (3,))
+    _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]), (4,))
     p.lattice_q = 27 if cfg.get("lattice") == "D3Q27" else 0
     p.frame_every = int(cfg.get("frame_every", 0))
     p.frame_front = int(cfg.get("frame_front", 0))

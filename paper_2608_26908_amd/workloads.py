@@ -76,6 +76,32 @@ WORKLOADS = {
         grav_axis=2, grav_sign=-1,
         init="lamellae", lam_width=12.0, lam_height=30.0,
         mu_inf=[0.0, 0.0], steps=10000, precision="fp32"),
+    # Case 3: three solids (alpha, beta, gamma) and the liquid, three
+    # components; App. B equilibrium compositions, solid-liquid slopes 1.2;
+    # the regular alpha-beta-gamma pattern, four periods across (4 lambda x 700)
+    "eutectic4": dict(
+        _COMMON, dim=2, n=[144, 700], periodic=[1, 0], N=4, nc=2,
+        gamma=[[0, 1, 1, 1], [1, 0, 1, 1], [1, 1, 0, 1], [1, 1, 1, 0]], delta=[[0] * 4] * 4,
+        c0=[[0.6, 0.2], [0.2, 0.6], [0.2, 0.2], [1.0 / 3.0, 1.0 / 3.0]],
+        dS=[0.24845199749997665, 0.24845199749997665, 0.15713484026367722, 0.0],
+        D=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [1.0, 1.0]],
+        G=1e-4, V=1e-3, y0=30.0, pull_axis=1,
+        tau_lb=0.7, gbeta=[5e-6, -2.5e-6], c_ref=[1.0 / 3.0, 1.0 / 3.0],
+        grav_axis=1, grav_sign=-1,
+        init="lamellae", lam_width=12.0, lam_height=30.0,
+        mu_inf=[0.0, 0.0], steps=20000, precision="fp32"),
+    # the same four-phase system in 3D (lamellae extruded along y), FP32
+    "eutectic4_3d": dict(
+        _COMMON, dim=3, n=[192, 192, 384], periodic=[1, 1, 0], N=4, nc=2,
+        gamma=[[0, 1, 1, 1], [1, 0, 1, 1], [1, 1, 0, 1], [1, 1, 1, 0]], delta=[[0] * 4] * 4,
+        c0=[[0.6, 0.2], [0.2, 0.6], [0.2, 0.2], [1.0 / 3.0, 1.0 / 3.0]],
+        dS=[0.24845199749997665, 0.24845199749997665, 0.15713484026367722, 0.0],
+        D=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [1.0, 1.0]],
+        G=5e-5, V=5e-4, y0=30.0, pull_axis=2,
+        tau_lb=0.75, gbeta=[5e-6, -2.5e-6], c_ref=[1.0 / 3.0, 1.0 / 3.0],
+        grav_axis=2, grav_sign=-1,
+        init="lamellae", lam_width=16.0, lam_height=30.0,
+        mu_inf=[0.0, 0.0], steps=10000, precision="fp32"),
 }
 
 

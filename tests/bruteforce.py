@@ -62,8 +62,12 @@ def dA_cs(q, gamma, delta):
 def h_funcs(phi):
     N = len(phi)
     h = [p * p * (3 - 2 * p) for p in phi]
-    if N == 3:
-        h = [x + 2 * phi[0] * phi[1] * phi[2] for x in h]
+    if N >= 3:
+        # + 2 phi_a times every product of two other phases
+        for a in range(N):
+            others = [phi[b] for b in range(N) if b != a]
+            h[a] += 2 * phi[a] * sum(others[i] * others[j] for i in range(len(others))
+                                     for j in range(i + 1, len(others)))
     return h
 
 

@@ -55,6 +55,17 @@ def busy_config(kind, n, **kw):
                        delta=[[0, 0.0, 0.04], [0.0, 0, 0.03], [0.04, 0.03, 0]],
                        chi=[[1.0, 0.2], [0.2, 0.8]], D=[[0.1, 0.0], [0.0, 0.05], [1.0, 0.7]],
                        y0=2.0, G=0.01)
+    elif kind == "quaternary2d":
+        cfg = workload("eutectic4", n=list(n), periodic=[1, 0], gbeta=[2e-3, -1e-3],
+                       delta=[[0, 0, 0, 0.04], [0, 0, 0, 0.03], [0, 0, 0, 0.02], [0.04, 0.03, 0.02, 0]],
+                       gamma=[[0, 1.3, 1.1, 1], [1.3, 0, 0.9, 0.8], [1.1, 0.9, 0, 1.2], [1, 0.8, 1.2, 0]],
+                       chi=[[1.0, 0.2], [0.2, 0.8]], D=[[0.1, 0.0], [0.0, 0.05], [0.02, 0.03], [1.0, 0.7]],
+                       y0=3.0, G=0.01)
+    elif kind == "quaternary3d":
+        cfg = workload("eutectic4_3d", n=list(n), periodic=[1, 0, 1], gbeta=[2e-3, -1e-3],
+                       delta=[[0, 0, 0, 0.04], [0, 0, 0, 0.03], [0, 0, 0, 0.02], [0.04, 0.03, 0.02, 0]],
+                       chi=[[1.0, 0.2], [0.2, 0.8]], D=[[0.1, 0.0], [0.0, 0.05], [0.02, 0.03], [1.0, 0.7]],
+                       y0=2.0, G=0.01)
     else:
         raise KeyError(kind)
     cfg.update(kw)
@@ -62,3 +73,4 @@ def busy_config(kind, n, **kw):
 
 
 KINDS = ["binary2d", "ternary2d", "ternary2d_nc2", "binary3d", "ternary3d_nc2"]
+KINDS4 = ["quaternary2d", "quaternary3d"]

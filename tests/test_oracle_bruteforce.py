@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from bruteforce import Step
-from inputs import KINDS, busy_config, random_state
+from inputs import KINDS, KINDS4, busy_config, random_state
 
 
 def _compare(oracle, cfg, st, steps):
@@ -77,3 +77,12 @@ def test_d3q27_vs_literal_evaluator(oracle, kind):
         a, b = sim.get(k), (s[k][perm] if k == "f" else s[k])
         scale = max(np.abs(b).max(), np.abs(s["f"]).max() if k == "u" else 0.0, 1e-300)
         assert np.abs(a - b).max() <= 1e-13 * scale, (k, np.abs(a - b).max(), scale)
+
+
+@pytest.mark.parametrize("kind", KINDS4)
+def test_four_phases_vs_literal_evaluator(oracle, kind):
+    """Three solids and the liquid (the paper's Case 3 system), every term on,
+    two solutes."""
+    n = [8, 8] if "2d" in kind else [4, 4, 4]
+    cfg = busy_config(kind, n)
+    _compare(oracle, cfg, random_state(cfg, 17), 3)

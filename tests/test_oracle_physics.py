@@ -97,18 +97,20 @@ def test_dendrite_invariants_1000_steps(oracle):
     assert np.abs(u).max() > 0
 
 
-def test_eutectic_invariants(oracle):
-    """Three phases, periodic in x, pulled gradient: sum phi = 1, solute and
-    mass conserved, no phase appears where its neighbourhood lacks it."""
+@pytest.mark.parametrize("name,n", [("eutectic2d", [64, 48]), ("eutectic4", [72, 64])])
+def test_eutectic_invariants(oracle, name, n):
+    """Three (or four: Case 3) phases, periodic in x, pulled gradient:
+    sum phi = 1, solute and mass conserved, no phase appears where its
+    neighbourhood lacks it."""
     from paper_2608_26908_amd.workloads import scaled
-    cfg = scaled("eutectic2d", [64, 48])
+    cfg = scaled(name, n)
     s = oracle.OracleSim(cfg)
     s0, m0 = s.total("solute"), s.total("mass")
     act0 = s.get("active")[0].astype(int)
     phi0 = s.get("phi")
     s.step(1)
     phi1 = s.get("phi")
-    for a in range(3):
+    for a in range(cfg["N"]):
         absent = (act0 & (1 << a)) == 0
         assert np.all(phi1[a][absent] == 0.0)
     s.step(299)
@@ -483,3 +485,43 @@ def test_moving_frame_is_a_translation(oracle):
         a, b = on.get(k), off.get(k)
         assert np.array_equal(a[:, lo:hi, :] if a.ndim == 3 else a[lo:hi], b[:, lo + S:hi + S, :]
                               if b.ndim == 3 else b[lo + S:hi + S]), k
+
+
+def test_four_phases_reduce_to_three_when_one_is_absent(oracle):
+    """With one solid absent everywhere, the four-phase step (Case 3 system)
+    is the three-phase step: the absent phase never appears (it is in no
+    cell's neighbourhood) and every other field follows the three-phase run."""
+    from inputs import busy_config, random_state
+    cfg3 = busy_config("ternary2d_nc2", [12, 10])
+    st3 = random_state(cfg3, 18)
+    emb = [0, 1, 3]  # alpha, beta, liquid -> slots 0, 1, 3; gamma (slot 2) absent
+
+    def embed(m, fill):
+        m = np.asarray(m, dtype=float)
+        out = np.full((4,) + m.shape[1:], fill)
+        out[emb] = m
+        return out
+
+    def embed2(m):
+        out = np.ones((4, 4))
+        out[np.ix_(emb, emb)] = np.asarray(m, dtype=float)
+        np.fill_diagonal(out, 0.0)
+        return out
+
+    cfg4 = dict(cfg3, N=4, gamma=embed2(cfg3["gamma"]).tolist(),
+                delta=(embed2(cfg3["delta"]) * (np.arange(4)[:, None] != 2) * (np.arange(4) != 2)).tolist(),
+                c0=embed(cfg3["c0"], 0.25).tolist(), dS=embed(cfg3["dS"], 0.1).tolist(),
+                D=embed(cfg3["D"], 0.01).tolist())
+    st4 = dict(st3, phi=embed(st3["phi"], 0.0))
+    s3, s4 = oracle.OracleSim(cfg3), oracle.OracleSim(cfg4)
+    for k in ("phi", "mu", "f", "u"):
+        s3.set(k, st3[k])
+        s4.set(k, st4[k])
+    s3.step(5)
+    s4.step(5)
+    p3, p4 = s3.get("phi"), s4.get("phi")
+    assert np.abs(p4[2]).max() == 0.0
+    assert np.abs(p4[emb] - p3).max() <= 1e-14
+    for k in ("mu", "f", "u"):
+        a, b = s4.get(k), s3.get(k)
+        assert np.abs(a - b).max() <= 1e-14 * max(np.abs(b).max(), 1e-30), k

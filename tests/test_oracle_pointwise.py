@@ -205,7 +205,7 @@ def test_projection_fixed_points(oracle):
 
 # ---------------- interpolation -------------------------------------------------
 
-@pytest.mark.parametrize("N", [2, 3])
+@pytest.mark.parametrize("N", [2, 3, 4])
 def test_h_partition_of_unity_and_derivative(oracle, N):
     rng = np.random.default_rng(20 + N)
     for _ in range(100):
@@ -227,6 +227,34 @@ def test_h_partition_of_unity_and_derivative(oracle, N):
         h, dh = oracle.interp_h(phi)
         assert np.array_equal(h, phi)
         assert np.abs(dh).max() == 0.0
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_h_reduces_to_two_phases_on_every_edge(oracle, N):
+    """On the edge phi_a + phi_b = 1 of the simplex the multiphase h is the
+    two-phase phi^2 (3 - 2 phi) for a and b and 0 for every other phase; on a
+    face (three phases present) it is the three-phase h."""
+    s = np.linspace(0.0, 1.0, 11)
+    for a in range(N):
+        for b in range(N):
+            if a == b:
+                continue
+            for t in s:
+                phi = np.zeros(N)
+                phi[a], phi[b] = t, 1 - t
+                h, _ = oracle.interp_h(phi)
+                assert h[a] == pytest.approx(t * t * (3 - 2 * t), abs=1e-15)
+                assert h[b] == pytest.approx((1 - t) ** 2 * (1 + 2 * t), abs=1e-15)
+                assert np.abs(np.delete(h, [a, b])).max(initial=0.0) == 0.0
+    if N == 4:
+        rng = np.random.default_rng(7)
+        for _ in range(20):
+            keep = rng.choice(4, 3, replace=False)
+            phi = np.zeros(4)
+            phi[keep] = rng.dirichlet(np.ones(3))
+            h4, _ = oracle.interp_h(phi)
+            h3, _ = oracle.interp_h(phi[keep])
+            assert np.abs(h4[keep] - h3).max() < 1e-15
 
 
 def test_normal_generator_statistics(oracle):
