@@ -223,6 +223,11 @@ def main():
     rf1 = run_gpu(dict(e2, frame_every=100, frame_front=16), "fp32", 1000, 50)
     print(f"# eutectic2d fp32: {rf0['mlups']:.1f} MLUPS, with the moving frame {rf1['mlups']:.1f}",
           file=sys.stderr, flush=True)
+    # four phases (three solids and the liquid, Case 3), 192 x 192 x 384 D3Q19
+    c4 = workload("eutectic4_3d")
+    r4 = run_gpu(c4, "fp32", min(args.steps, 100), args.warmup)
+    print(f"# fp32 four phases: {r4['mlups']:.1f} MLUPS, {r4['ms_per_step']:.3f} ms/step", file=sys.stderr,
+          flush=True)
     copy_gbs = copy_bandwidth()
     print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     b32 = bytes_per_lup(cfg, 4)
@@ -262,6 +267,13 @@ def main():
     line["moving_frame"] = {"workload": "eutectic2d 1024x512 FP32, front search every 100 steps, front kept at 16",
                             "value": round(rf1["mlups"], 2), "unit": "MLUPS",
                             "without_frame": round(rf0["mlups"], 2)}
+    b4 = bytes_per_lup(c4, 4)
+    line["four_phase"] = {"workload": "eutectic4_3d: 192x192x384 D3Q19, 4 phases, 2 solutes, FP32",
+                          "value": round(r4["mlups"], 2), "unit": "MLUPS",
+                          "ms_per_step": round(r4["ms_per_step"], 4), "k_phi_ms": round(r4["k_phi_ms"], 4),
+                          "k_mulbm_ms": round(r4["k_mulbm_ms"], 4), "bytes_per_lup": b4,
+                          "roofline_frac": round(b4 * r4["cells"] / (r4["k_mulbm_ms"] * 1e-3) / 1e9
+                                                 / HBM_PEAK_GBS, 4)}
     b27 = bytes_per_lup(c27, 4)
     line["d3q27"] = {"value": round(r27["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(r27["ms_per_step"], 4),
                      "k_phi_ms": round(r27["k_phi_ms"], 4), "k_mulbm_ms": round(r27["k_mulbm_ms"], 4),

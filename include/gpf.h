@@ -98,13 +98,13 @@ typedef struct {
   int32_t precision;      /* gpf_precision: FP64, or FP32 storage and arithmetic */
   int32_t potential;      /* gpf_potential: OBSTACLE (the paper) or WELL (test only) */
   double dt, eps, tau_pf; /* time step, interface parameter eps, relaxation tau of Eq. (PhfGrand) */
-  double gamma[3][3];     /* interface energies gamma_ab, symmetric */
-  double delta[3][3];     /* cubic anisotropy strength per pair, symmetric */
+  double gamma[4][4];     /* interface energies gamma_ab, symmetric */
+  double delta[4][4];     /* cubic anisotropy strength per pair, symmetric */
   double chi[2][2];       /* susceptibility, SPD, common to all phases: C^a = c0[a] + chi mu */
-  double c0[3][2];
-  double dS[3];           /* grand potential psi^a gets + dS[a] (T - T_E) */
+  double c0[4][2];
+  double dS[4];           /* grand potential psi^a gets + dS[a] (T - T_E) */
   double T_E, T_iso;      /* eutectic / equilibrium temperature; temperature when G = 0 */
-  double D[3][2];         /* diffusivity per phase and solute (solids 0 in the paper) */
+  double D[4][2];         /* diffusivity per phase and solute (solids 0 in the paper) */
   double G, V, y0;        /* frozen gradient T = T_E + G (x_pull - y0 - V n), V in cells/step */
   int32_t pull_axis;
   double tau_lb, rho0;    /* BGK relaxation time (> 1/2) and reference density */
@@ -112,7 +112,7 @@ typedef struct {
   double c_ref[2];        /* reference liquid composition of Eq. (buoyancy) */
   int32_t grav_axis, grav_sign; /* unit gravity vector = grav_sign * e_{grav_axis} */
   double h_drag, W0;      /* drag kappa = 2 nu h / W0 of G_D, nu = (tau_lb - 1/2)/3 */
-  double eta[3];          /* shrinkage force G_S of Eq. (shrinkage): eta_a = (rho_a - rho_liq) / rho_liq
+  double eta[4];          /* shrinkage force G_S of Eq. (shrinkage): eta_a = (rho_a - rho_liq) / rho_liq
                              per phase (liquid 0); G_S = sum_a eta_a (phi^{n+1}_a - phi^n_a) n_a per
                              lattice step, n_a the unit normal of phi^{n+1}_a from central differences.
                              All 0: off.  gpf_adjoint refuses a context with G_S on. */
@@ -143,7 +143,9 @@ typedef struct {
  * mu^0 = mu_inf + noise_sigma * z with z standard normal from a
  * counter-based SplitMix64 + Box-Muller stream keyed by `seed`
  * (z index = cell * nc + i); f^0 = w_k rho0; U = 0.
- * n_phases: 2 or 3.  n_components: 2 or 3 (nc = n_components - 1).
+ * n_phases: 2, 3 or 4 (four: three solids and the liquid, the paper's Case 3
+ * system, built for n_components = 3 only).  n_components: 2 or 3
+ * (nc = n_components - 1).
  * Errors: GPF_ERR_ARG (NULL), GPF_ERR_PARAM (tau_lb <= 1/2, dt, dx, eps,
  * tau_pf <= 0, explicit stability bound exceeded, chi not SPD, axes out of
  * range, lattice/dim mismatch), GPF_ERR_UNSUPPORTED (N, nc, dim outside the

@@ -74,11 +74,29 @@ __device__ __forceinline__ void load_stencil(const KP<R>& p, const R* __restrict
       }
 }
 
-// d^2 h_b / dphi_a dphi_g
+// d^2 h_b / dphi_a dphi_g.  For N >= 3, with h_b's extra term 2 phi_b e_b:
+// 2 (delta_ab de_b/dphi_g + delta_gb de_b/dphi_a + phi_b d2e_b/dphi_a dphi_g),
+// de_b/dphi_g = sum of the phases other than b and g (g != b), and
+// d2e_b/dphi_a dphi_g = 1 for distinct a, g, b.
 template <int N, class R>
 __device__ __forceinline__ R d2h(const R (&ph)[N], int b, int a, int g) {
   R r = (a == b && g == b) ? R(6) - R(12) * ph[b] : R(0);
-  if (N == 3 && a != g) r += R(2) * ph[3 - a - g];
+  if constexpr (N == 3) {
+    if (a != g) r += R(2) * ph[3 - a - g];
+  } else if constexpr (N >= 4) {
+    if (a != g) {
+      if (a == b || g == b) {
+        const int o = (a == b) ? g : a;
+        R rest = R(0);
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+          if (k != b && k != o) rest += ph[k];
+        r += R(2) * rest;
+      } else {
+        r += R(2) * ph[b];
+      }
+    }
+  }
   return r;
 }
 

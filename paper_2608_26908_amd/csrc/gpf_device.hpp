@@ -86,16 +86,16 @@ template <class R> struct KP {
   int pull_axis, grav_axis;
   R dx, dt, eps, rate;    // rate = dt / (tau_pf eps)
   R tau_pf;
-  R gamma[3][3], delta[3][3];
-  R chi[2][2], c0[3][2], dS[3];
+  R gamma[4][4], delta[4][4];
+  R chi[2][2], c0[4][2], dS[4];
   // chemical potentials are stored as mu - mu_ref (mu_ref = far-field mu in
   // FP32 storage, 0 in FP64), so C^a = c0s[a] + chi (mu - mu_ref)
-  R mu_ref[2], c0s[3][2];
-  double mu_ref_d[2], c0s_d[3][2];
-  R D[3][2];
+  R mu_ref[2], c0s[4][2];
+  double mu_ref_d[2], c0s_d[4][2];
+  R D[4][2];
   R G, tdev_iso, T_E;     // T - T_E = G (x_pull - shift) if G != 0, else tdev_iso
   R tau_lb, rho0, gbeta[2], c_ref[2], grav_sign, kappa, lid_u;
-  R eta[3];               // shrinkage (rho_a - rho_liq) / rho_liq per phase
+  R eta[4];               // shrinkage (rho_a - rho_liq) / rho_liq per phase
   int shrink;             // some eta != 0
   R qmin2;                // |q|^2 below which the anisotropy direction is undefined
   R w[27];                // lattice weights in R
@@ -177,24 +177,55 @@ __device__ __forceinline__ void dAdq_vjp(const R (&q)[D], R gamma, R delta, R qm
   for (int a = 0; a < D; ++a) ddelta_w += out[a].d * w[a];
 }
 
-// Interpolation h_a(phi): N = 2: phi^2 (3 - 2 phi); N = 3 adds 2 phi_0 phi_1 phi_2.
+// Interpolation h_a(phi): phi_a^2 (3 - 2 phi_a), plus for N >= 3
+// 2 phi_a e_a with e_a the sum over pairs of the other phases of their
+// product (N = 3: the product of the other two, so 2 phi_0 phi_1 phi_2 for
+// every phase).  Sum h = 1 on the simplex.
+template <int N, class R>
+__device__ __forceinline__ R pair_sum_others(const R (&ph)[N], int b) {
+  R e = R(0);
+#pragma unroll
+  for (int g = 0; g < N; ++g)
+#pragma unroll
+    for (int k = g + 1; k < N; ++k)
+      if (g != b && k != b) e += ph[g] * ph[k];
+  return e;
+}
 template <int N, class R>
 __device__ __forceinline__ void interp_h(const R (&ph)[N], R (&h)[N]) {
-  R tri = (N == 3) ? R(2) * ph[0] * ph[1] * ph[N - 1] : R(0);
+  if constexpr (N == 3) {
+    const R tri = R(2) * ph[0] * ph[1] * ph[2];
 #pragma unroll
-  for (int b = 0; b < N; ++b) h[b] = ph[b] * ph[b] * (R(3) - R(2) * ph[b]) + tri;
+    for (int b = 0; b < N; ++b) h[b] = ph[b] * ph[b] * (R(3) - R(2) * ph[b]) + tri;
+  } else {
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      h[b] = ph[b] * ph[b] * (R(3) - R(2) * ph[b]);
+      if (N >= 4) h[b] += R(2) * ph[b] * pair_sum_others<N, R>(ph, b);
+    }
+  }
 }
 
 // dh_b / dphi_a, a fixed.
 template <int N, class R>
 __device__ __forceinline__ R dh(const R (&ph)[N], int b, int a) {
   R r = (a == b) ? R(6) * ph[b] * (R(1) - ph[b]) : R(0);
-  if (N == 3) {
+  if constexpr (N == 3) {
     R other = R(1);
 #pragma unroll
     for (int g = 0; g < N; ++g)
       if (g != a) other *= ph[g];
     r += R(2) * other;
+  } else if constexpr (N >= 4) {
+    if (a == b) {
+      r += R(2) * pair_sum_others<N, R>(ph, b);
+    } else {
+      R rest = R(0);  // d e_b / d phi_a: the phases other than a and b
+#pragma unroll
+      for (int g = 0; g < N; ++g)
+        if (g != a && g != b) rest += ph[g];
+      r += R(2) * ph[b] * rest;
+    }
   }
   return r;
 }
@@ -203,14 +234,15 @@ __device__ __forceinline__ R dh(const R (&ph)[N], int b, int a) {
 // selected by `mask` (the others are set to 0): sort the selected values
 // descending, take the largest j with u_j - (sum_{i<=j} u_i - 1)/j > 0,
 // theta = (sum_{i<=j} u_i - 1)/j, result max(v - theta, 0) (Held, Wolfe and
-// Crowder 1974).  N <= 3: a sorting network on fixed-size arrays, unselected
-// entries sorted last.
+// Crowder 1974).  A sorting network on fixed-size arrays (3 or 4 slots),
+// unselected entries sorted last.
 template <int N, class R>
 __device__ __forceinline__ void project_masked(unsigned mask, const R (&v)[N], R (&out)[N], R& theta) {
-  R u[3];
-  bool on[3];
+  constexpr int M = N > 3 ? N : 3;
+  R u[M];
+  bool on[M];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < M; ++i) {
     on[i] = (i < N) && ((mask >> i) & 1u);
     u[i] = (i < N) ? v[i] : R(0);
   }
@@ -222,20 +254,26 @@ __device__ __forceinline__ void project_masked(unsigned mask, const R (&v)[N], R
       bool b = on[i]; on[i] = on[j]; on[j] = b;
     }
   };
-  cs(0, 1);
-  cs(1, 2);
-  cs(0, 1);
+  if constexpr (M == 3) {
+    cs(0, 1);
+    cs(1, 2);
+    cs(0, 1);
+  } else {
+    cs(0, 1);
+    cs(2, 3);
+    cs(0, 2);
+    cs(1, 3);
+    cs(1, 2);
+  }
   R csum = u[0];
   theta = u[0] - R(1);  // j = 1 always qualifies
-  if (on[1]) {
-    csum += u[1];
-    const R t = (csum - R(1)) / R(2);
-    if (u[1] - t > R(0)) theta = t;
-  }
-  if (on[2]) {
-    csum += u[2];
-    const R t = (csum - R(1)) / R(3);
-    if (u[2] - t > R(0)) theta = t;
+#pragma unroll
+  for (int j = 1; j < M; ++j) {
+    if (on[j]) {
+      csum += u[j];
+      const R t = (csum - R(1)) / R(j + 1);
+      if (u[j] - t > R(0)) theta = t;
+    }
   }
 #pragma unroll
   for (int i = 0; i < N; ++i)

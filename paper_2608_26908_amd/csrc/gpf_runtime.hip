@@ -148,14 +148,14 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
   k.eps = (R)p.eps;
   k.rate = (R)(p.dt / (p.tau_pf * p.eps));
   k.tau_pf = (R)p.tau_pf;
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
       k.gamma[a][b] = (R)p.gamma[a][b];
       k.delta[a][b] = (R)p.delta[a][b];
     }
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) k.chi[i][j] = (R)p.chi[i][j];
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 4; ++a) {
     for (int i = 0; i < 2; ++i) {
       k.c0[a][i] = (R)p.c0[a][i];
       k.D[a][i] = (R)p.D[a][i];
@@ -166,7 +166,7 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
     k.mu_ref_d[i] = (p.precision == GPF_FP32 && i < c->nc) ? p.mu_inf[i] : 0.0;
     k.mu_ref[i] = (R)k.mu_ref_d[i];
   }
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 4; ++a)
     for (int i = 0; i < 2; ++i) {
       double s = p.c0[a][i];
       for (int j = 0; j < c->nc; ++j) s += p.chi[i][j] * k.mu_ref_d[j];
@@ -187,7 +187,7 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
   k.kappa = (R)(2.0 * nu * p.h_drag / p.W0);
   k.lid_u = (R)p.lid_u;
   k.shrink = 0;
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 4; ++a) {
     k.eta[a] = (a < c->N) ? (R)p.eta[a] : R(0);
     if (k.eta[a] != R(0)) k.shrink = 1;
   }
@@ -667,7 +667,8 @@ const Ops* pick_nc(int nc) {
 }
 template <int D, int Q, class R>
 const Ops* pick_n(int N, int nc) {
-  return N == 2 ? pick_nc<D, Q, 2, R>(nc) : pick_nc<D, Q, 3, R>(nc);
+  // four phases only with two solutes (three components), as Case 3
+  return N == 2 ? pick_nc<D, Q, 2, R>(nc) : (N == 3 ? pick_nc<D, Q, 3, R>(nc) : Impl<D, Q, 4, 2, R>::ops());
 }
 template <class R>
 const Ops* pick_d(int Q, int N, int nc) {
@@ -686,9 +687,11 @@ int validate(gpf_ctx* c, const gpf_grid* g, int N, int K, const gpf_params* p) {
       (g->dim == 3 && p->lattice != GPF_D3Q19 && p->lattice != GPF_D3Q27))
     return fail(c, GPF_ERR_PARAM, "lattice %d does not match dim %d (D2Q9 in 2D, D3Q19 or D3Q27 in 3D)",
                 p->lattice, g->dim);
-  if (N < 2 || N > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_phases must be 2 or 3, got %d", N);
+  if (N < 2 || N > 4) return fail(c, GPF_ERR_UNSUPPORTED, "n_phases must be 2, 3 or 4, got %d", N);
+  if (N == 4 && K != 3)
+    return fail(c, GPF_ERR_UNSUPPORTED, "four phases are built for three components (n_components = 3)");
   if (K < 2 || K > 3) return fail(c, GPF_ERR_UNSUPPORTED, "n_components must be 2 or 3, got %d", K);
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 4; ++a)
     if (!std::isfinite(p->eta[a])) return fail(c, GPF_ERR_PARAM, "eta[%d] is not finite", a);
   if (p->frame_every < 0) return fail(c, GPF_ERR_PARAM, "frame_every must be >= 0");
   if (p->frame_every > 0) {
@@ -795,7 +798,9 @@ int init_state(gpf_ctx* c, uint64_t seed) {
       sol = solid_fraction(std::sqrt(r2) - p.init_radius * dx, p.eps);
     } else if (p.init_kind == GPF_INIT_LAMELLAE) {
       sol = solid_fraction(((double)x[p.pull_axis] - p.lam_height) * dx, p.eps);
-      if (c->N == 3 && p.lam_width > 0) solid = (int)(((int64_t)std::floor((double)x[0] / p.lam_width)) % 2);
+      // the N - 1 solids take turns along x, lam_width cells each
+      if (c->N >= 3 && p.lam_width > 0)
+        solid = (int)(((int64_t)std::floor((double)x[0] / p.lam_width)) % (c->N - 1));
     }
     phi[(size_t)solid * cells + P] = sol;
     phi[(size_t)(c->N - 1) * cells + P] = 1.0 - sol;
@@ -881,8 +886,8 @@ void free_all(gpf_ctx* c) {
 int set_named(gpf_ctx* c, gpf_params& p, const char* name, double v) {
   const int l = c->N - 1;
   if (!std::strcmp(name, "delta")) {
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
         if (p.delta[a][b] != 0.0) p.delta[a][b] = v;
   } else if (!std::strcmp(name, "tau_pf")) {
     p.tau_pf = v;
@@ -1097,7 +1102,7 @@ int gpf_adjoint(gpf_ctx* c, const double* dL_dphi, size_t count, const char* con
   if (count != (size_t)c->N * (size_t)c->cells)
     return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, (size_t)c->N * (size_t)c->cells);
   if (n_names > gpf::NG) return fail(c, GPF_ERR_ARG, "at most %d parameters", gpf::NG);
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 4; ++a)
     if (c->prm.eta[a] != 0.0)
       return fail(c, GPF_ERR_UNSUPPORTED, "the adjoint does not include the shrinkage force (eta != 0)");
   if (c->prm.frame_every > 0)

@@ -42,16 +42,16 @@ class ParamsC(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int32), ("precision", ctypes.c_int32), ("potential", ctypes.c_int32),
         ("dt", ctypes.c_double), ("eps", ctypes.c_double), ("tau_pf", ctypes.c_double),
-        ("gamma", (ctypes.c_double * 3) * 3), ("delta", (ctypes.c_double * 3) * 3),
-        ("chi", (ctypes.c_double * 2) * 2), ("c0", (ctypes.c_double * 2) * 3),
-        ("dS", ctypes.c_double * 3), ("T_E", ctypes.c_double), ("T_iso", ctypes.c_double),
-        ("D", (ctypes.c_double * 2) * 3),
+        ("gamma", (ctypes.c_double * 4) * 4), ("delta", (ctypes.c_double * 4) * 4),
+        ("chi", (ctypes.c_double * 2) * 2), ("c0", (ctypes.c_double * 2) * 4),
+        ("dS", ctypes.c_double * 4), ("T_E", ctypes.c_double), ("T_iso", ctypes.c_double),
+        ("D", (ctypes.c_double * 2) * 4),
         ("G", ctypes.c_double), ("V", ctypes.c_double), ("y0", ctypes.c_double),
         ("pull_axis", ctypes.c_int32),
         ("tau_lb", ctypes.c_double), ("rho0", ctypes.c_double),
         ("gbeta", ctypes.c_double * 2), ("c_ref", ctypes.c_double * 2),
         ("grav_axis", ctypes.c_int32), ("grav_sign", ctypes.c_int32),
-        ("h_drag", ctypes.c_double), ("W0", ctypes.c_double), ("eta", ctypes.c_double * 3),
+        ("h_drag", ctypes.c_double), ("W0", ctypes.c_double), ("eta", ctypes.c_double * 4),
         ("lid_u", ctypes.c_double),
         ("init_kind", ctypes.c_int32), ("init_center", ctypes.c_double * 3),
         ("init_radius", ctypes.c_double), ("lam_width", ctypes.c_double),

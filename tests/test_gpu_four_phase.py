@@ -1,0 +1,127 @@
+"""GPU parity with four phases (three solids and the liquid, three
+components: the paper's Case 3 system) against the FP64 oracle, forward and
+adjoint."""
+import numpy as np
+import pytest
+
+from gpu_helpers import STATE, field_floor, gpu_from, oracle_from, read_state, rel_err, window_step
+from inputs import KINDS4, busy_config, random_state
+from paper_2608_26908_amd.workloads import scaled, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+RAGGED = {"2d": [100, 37], "3d": [70, 9, 11]}
+
+
+def _cmp(gpu, ora, tol=TOL64):
+    ref = {k: ora.get(k) for k in STATE}
+    for k in STATE:
+        e = rel_err(gpu.read(k), ref[k], field_floor(k, ref))
+        assert e <= tol, (k, e)
+
+
+@pytest.mark.parametrize("kind,lattice", [("quaternary2d", None), ("quaternary3d", None),
+                                          ("quaternary3d", "D3Q27")])
+def test_one_step_random_state_fp64(oracle, kind, lattice):
+    cfg = busy_config(kind, RAGGED["2d" if "2d" in kind else "3d"])
+    if lattice:
+        cfg["lattice"] = lattice
+    st = random_state(cfg, 9)
+    g = gpu_from(cfg, st, "fp64")
+    o = oracle_from(cfg, st)
+    g.step(1)
+    o.step(1)
+    _cmp(g, o)
+    assert np.array_equal(g.read("flags"), o.get("active"))
+    for k in ("rho", "c", "T"):
+        assert rel_err(g.read(k), o.get(k)) <= TOL64, k
+
+
+@pytest.mark.parametrize("name,n,steps", [("eutectic4", [72, 96], 200), ("eutectic4_3d", [48, 48, 64], 50)])
+def test_workload_fp64(oracle, name, n, steps):
+    from paper_2608_26908_amd.gpf import Sim
+    cfg = scaled(name, n)
+    g, o = Sim(cfg, precision="fp64"), oracle.OracleSim(cfg)
+    g.step(steps)
+    o.step(steps)
+    _cmp(g, o)
+    assert np.abs(g.reduce("solute") - o.total("solute")).max() <= 1e-12 * np.abs(o.total("solute")).max()
+
+
+@pytest.mark.parametrize("name,n", [("eutectic4", [144, 256]), ("eutectic4_3d", [48, 48, 64])])
+def test_fp32_within_tolerance_after_100_steps(oracle, name, n):
+    from paper_2608_26908_amd.gpf import Sim
+    cfg = scaled(name, n, gbeta=[2e-3, -1e-3])
+    g, o = Sim(cfg, precision="fp32"), oracle.OracleSim(cfg)
+    g.step(100)
+    o.step(100)
+    dphi = np.abs(g.read("phi") - o.get("phi")).max()
+    ug, uo = g.read("u"), o.get("u")
+    rl2 = np.sqrt(((ug - uo) ** 2).sum() / (uo ** 2).sum())
+    print(f"FP32 vs FP64 oracle, four phases, {name} {n}, 100 steps: "
+          f"max|dphi| {dphi:.2e}, rel-L2(U) {rl2:.2e}")
+    assert dphi <= 1e-5, dphi
+    assert rl2 <= 1e-4, rl2
+
+
+def test_full_size_sampled_step_fp32(oracle):
+    from paper_2608_26908_amd.gpf import Sim
+    cfg = workload("eutectic4_3d")
+    g = Sim(cfg, precision="fp32")
+    g.step(20)
+    st = read_state(g)
+    g.step(1)
+    after = read_state(g)
+    # lamella junctions (alpha|beta, beta|gamma, gamma|alpha) at the front, bulk, corners
+    pts = [(16, 40, 30), (32, 100, 30), (47, 7, 29), (0, 0, 31), (100, 100, 200), (191, 191, 383)]
+    tol = dict(phi=1e-5, mu=1e-5, f=1e-5, u=1e-3)
+    for pt in pts:
+        ref = window_step(cfg, st, 20, pt)
+        sl = (slice(None),) + tuple(reversed(pt))
+        for k in STATE:
+            got = after[k][sl]
+            scale = max(np.abs(after[k]).max(), field_floor(k, after), 1e-30)
+            assert np.abs(got - ref[k]).max() <= tol[k] * scale, (pt, k, got, ref[k])
+
+
+@pytest.mark.parametrize("kind", KINDS4)
+def test_adjoint_dot_product_fp64(oracle, kind):
+    n = [36, 22] if "2d" in kind else [12, 10, 11]
+    cfg = busy_config(kind, n)
+    st = random_state(cfg, 23)
+    steps, K = 6, 3
+    g = gpu_from(cfg, st, "fp64")
+    g.record(K)
+    g.step(steps)
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal((cfg["N"],) + g.shape)
+    g.adjoint(w, [])
+    o = oracle_from(cfg, st)
+    for field in ("phi", "mu", "u", "f"):
+        lam = g.adjoint_state(field)
+        v = rng.standard_normal(lam.shape)
+        t = o.tangent_cs(steps, field, v, "phi")
+        lhs, rhs = float((w * t).sum()), float((lam * v).sum())
+        assert abs(lhs - rhs) <= 1e-9 * max(abs(lhs), abs(rhs), 1e-30), (field, lhs, rhs)
+
+
+def test_parameter_gradients_match_complex_step_fp64(oracle):
+    """dL/d(delta, tau, D, D1, g beta, g beta1) on the four-phase eutectic."""
+    from paper_2608_26908_amd.gpf import Sim
+    cfg = scaled("eutectic4", [36, 40], lam_height=10.0, y0=10.0, gbeta=[2e-3, -1e-3],
+                 delta=[[0, 0, 0, 0.03], [0, 0, 0, 0.02], [0, 0, 0, 0.01], [0.03, 0.02, 0.01, 0]])
+    steps = 30
+    t = dict(cfg, tau_pf=1.1, gbeta=[3e-3, -2e-3])
+    ts = oracle.OracleSim(t)
+    ts.step(steps)
+    target = ts.get("phi")
+    g = Sim(cfg, precision="fp64")
+    g.record(8)
+    g.step(steps)
+    names = ["delta", "tau_pf", "D", "D1", "gbeta", "gbeta1"]
+    grads = g.adjoint(g.read("phi") - target, names)
+    o = oracle.OracleSim(cfg)
+    for name, gv in zip(names, grads):
+        L, ref = o.loss_grad_cs(steps, target, name)
+        assert gv == pytest.approx(ref, rel=1e-8, abs=1e-14 * abs(L)), (name, gv, ref)
