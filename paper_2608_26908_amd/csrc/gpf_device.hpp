@@ -5,6 +5,7 @@
 // Storage precision R is float or double; arithmetic is carried out in R.
 // Every field is structure-of-arrays [component][z][y][x], x fastest.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -135,6 +136,14 @@ template <class R> __device__ __forceinline__ R value_of(Dual<R> x) { return x.v
 // a_c = 1 and grad a_c = 0 below |q|^2 = qmin2.  T is R or Dual<R>.
 template <int D, class T, class R>
 __device__ __forceinline__ void dAdq(const T (&q)[D], T gamma, T delta, R qmin2, T (&out)[D]) {
+  if constexpr (std::is_same<T, R>::value) {
+    // isotropic pair: the general expression reduces to 2 gamma q exactly
+    if (delta == R(0)) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) out[a] = R(2) * gamma * q[a];
+      return;
+    }
+  }
   T q2 = T(R(0)), q4 = T(R(0));
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -162,6 +171,14 @@ __device__ __forceinline__ void dAdq(const T (&q)[D], T gamma, T delta, R qmin2,
 template <int D, class R>
 __device__ __forceinline__ void dAdq_vjp(const R (&q)[D], R gamma, R delta, R qmin2, const R (&w)[D],
                                          R (&Hw)[D], R& ddelta_w) {
+  if (delta == R(0)) {
+    // isotropic pair: H = 2 gamma I exactly; the delta derivative is not
+    // asked for pairs without anisotropy
+#pragma unroll
+    for (int a = 0; a < D; ++a) Hw[a] = R(2) * gamma * w[a];
+    ddelta_w = R(0);
+    return;
+  }
   Dual<R> qd[D], out[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) qd[a] = Dual<R>(q[a], w[a]);
