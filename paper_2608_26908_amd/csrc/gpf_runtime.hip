@@ -64,8 +64,13 @@ struct gpf_ctx {
   // adjoint: checkpoints every rec_every steps from step rec_start
   int64_t rec_every = 0, rec_start = 0;
   std::vector<StateBuf> ckpt;
-  std::vector<StateBuf> tape;      // recomputed states of one segment (no f of their own)
-  DevBuf tape_f[2];                // populations of the recomputed states, alternating
+  // two tapes of recomputed segment states (no f of their own): the segment
+  // being reversed reads one while the previous segment is recomputed into
+  // the other on a second stream (default priority)
+  std::vector<StateBuf> tape[2];
+  DevBuf tape_f[2][2];             // populations of each tape's states, alternating
+  hipStream_t side = nullptr;
+  hipEvent_t ev_free[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
   StateBuf lam[2];                 // adjoint state (phi, mu, U, post-streaming f)
   DevBuf t_phil, t_w, t_rbar, t_part, t_acc, t_slices, t_rflag, t_fflag, t_fbuf, t_cbuf;
   int lam_cur = 0;                 // lam[lam_cur] holds the adjoint of the earliest state reached
@@ -258,7 +263,7 @@ struct Impl {
   }
 
   static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& in, const SP& out, R ts,
-                          hipEvent_t* ev) {
+                          hipStream_t st, hipEvent_t* ev) {
     constexpr int TX = 64, TY = kTileY;
     const int tiles_x = (int)((c->n[0] + TX - 1) / TX), tiles_y = (int)((c->n[1] + TY - 1) / TY);
     auto grid = [&](int zc) {
@@ -266,19 +271,19 @@ struct Impl {
       return dim3((unsigned)tiles_x * (unsigned)tiles_y * (unsigned)tiles_z);
     };
     const dim3 block(TX * TY);
-    if (ev) (void)hipEventRecord(ev[0], c->stream);
-    hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid(kZChunkPhi), block, 0, c->stream, k, in.phi,
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid(kZChunkPhi), block, 0, st, k, in.phi,
                        in.mu, out.phi, ts, tiles_x, tiles_y, kZChunkPhi);
-    if (ev) (void)hipEventRecord(ev[1], c->stream);
+    if (ev) (void)hipEventRecord(ev[1], st);
     if (k.shrink)
-      hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, true>), grid(kZChunkMu), block, 0, c->stream, k,
+      hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, true>), grid(kZChunkMu), block, 0, st, k,
                          in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y,
                          kZChunkMu);
     else
-      hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, false>), grid(kZChunkMu), block, 0, c->stream, k,
+      hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, false>), grid(kZChunkMu), block, 0, st, k,
                          in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y,
                          kZChunkMu);
-    if (ev) (void)hipEventRecord(ev[2], c->stream);
+    if (ev) (void)hipEventRecord(ev[2], st);
   }
 
   // Moving frame.  Reading (the paper names the approach only): every
@@ -334,7 +339,7 @@ struct Impl {
     for (int64_t it = 0; it < nsteps; ++it) {
       const int s = c->cur, t = 1 - c->cur;
       const R ts = (R)tshift(c, c->step);
-      launch_step(c, k, cur(c, s), cur(c, t), ts, kernel_ms ? ev : nullptr);
+      launch_step(c, k, cur(c, s), cur(c, t), ts, c->stream, kernel_ms ? ev : nullptr);
       HIP_OR_FAIL(c, hipGetLastError());
       if (kernel_ms) {
         HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
@@ -572,17 +577,28 @@ struct Impl {
       if (!rc) rc = dev_alloc(c, c->t_cbuf, (size_t)(1 + 2 * D) * N * cs);
       if (rc) return rc;
     }
-    while ((int64_t)c->tape.size() < K - 1) {
-      StateBuf s;
-      rc = dev_alloc(c, s.phi, N * cs);
-      if (!rc) rc = dev_alloc(c, s.mu, NC * cs);
-      if (!rc) rc = dev_alloc(c, s.u, D * cs);
-      if (!rc) rc = dev_alloc(c, s.dr, cs);
-      if (rc) return rc;
-      c->tape.push_back(s);
+    const int64_t nseg = (total + K - 1) / K;
+    const int ntape = nseg > 1 ? 2 : 1;
+    for (int b = 0; b < ntape; ++b) {
+      while ((int64_t)c->tape[b].size() < K - 1) {
+        StateBuf s;
+        rc = dev_alloc(c, s.phi, N * cs);
+        if (!rc) rc = dev_alloc(c, s.mu, NC * cs);
+        if (!rc) rc = dev_alloc(c, s.u, D * cs);
+        if (!rc) rc = dev_alloc(c, s.dr, cs);
+        if (rc) return rc;
+        c->tape[b].push_back(s);
+      }
+      for (int i = 0; i < 2 && K > 1; ++i)
+        if (!c->tape_f[b][i].ptr && (rc = dev_alloc(c, c->tape_f[b][i], Q * cs))) return rc;
     }
-    for (int i = 0; i < 2 && K > 1; ++i)
-      if (!c->tape_f[i].ptr && (rc = dev_alloc(c, c->tape_f[i], Q * cs))) return rc;
+    if (ntape > 1 && !c->side) {
+      HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+      for (int b = 0; b < 2; ++b) {
+        HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->ev_free[b], hipEventDisableTiming));
+        HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->ev_done[b], hipEventDisableTiming));
+      }
+    }
     gpf::KP<R> k = make_kp<R>(c);
     // lam^N = (seed, 0, 0, 0)
     StateBuf* li = &c->lam[0];
@@ -600,28 +616,43 @@ struct Impl {
     const int64_t nparts = (int64_t)3 * lin_blocks(c->cells, gpf::ADJ_BLOCK);
     hipLaunchKernelGGL((gpf::k_fill<double>), dim3(lin_blocks(nparts * gpf::NG, 256)), dim3(256), 0, c->stream,
                        static_cast<double*>(c->t_part.ptr), nparts * gpf::NG, 0.0);
-    const int64_t nseg = (total + K - 1) / K;
+    // slot j of segment sg in tape b holds X^{n0 + j} (slot 0 is the
+    // checkpoint) and rho - rho0 of step n0 + j - 1; the tape's populations
+    // alternate between its two buffers
+    auto slot = [&](int b, int64_t sg, int64_t j) -> SP {
+      if (j == 0) return sp(c->ckpt[sg]);
+      SP s = sp(c->tape[b][j - 1]);
+      s.f = P(c->tape_f[b][j % 2]);
+      return s;
+    };
+    auto seg_len = [&](int64_t sg) { return std::min<int64_t>(K, total - sg * K); };
+    auto recompute = [&](int b, int64_t sg, hipStream_t st) {
+      const int64_t n0 = c->rec_start + sg * K;
+      for (int64_t j = 0; j < seg_len(sg) - 1; ++j)
+        launch_step(c, k, slot(b, sg, j), slot(b, sg, j + 1), (R)tshift(c, n0 + j), st, nullptr);
+    };
+    recompute(0, nseg - 1, c->stream);
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+      const int b = (int)((nseg - 1 - sgi) & 1);
+      if (sgi > 0) {
+        // the previous segment goes into the other tape once the reverse of
+        // the segment that used it (already queued) is done
+        HIP_OR_FAIL(c, hipEventRecord(c->ev_free[1 - b], c->stream));
+        HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->ev_free[1 - b], 0));
+        recompute(1 - b, sgi - 1, c->side);
+        HIP_OR_FAIL(c, hipEventRecord(c->ev_done[1 - b], c->side));
+      }
       const int64_t n0 = c->rec_start + sgi * K;
-      const int64_t len = std::min<int64_t>(K, total - sgi * K);
-      // recompute the segment: slot j holds X^{n0 + j} (slot 0 is the checkpoint)
-      // and rho - rho0 of step n0 + j - 1; its populations alternate between two buffers
-      auto slot = [&](int64_t j) -> SP {
-        if (j == 0) return sp(c->ckpt[sgi]);
-        SP s = sp(c->tape[j - 1]);
-        s.f = P(c->tape_f[j % 2]);
-        return s;
-      };
-      for (int64_t j = 0; j < len - 1; ++j)
-        launch_step(c, k, slot(j), slot(j + 1), (R)tshift(c, n0 + j), nullptr);
+      const int64_t len = seg_len(sgi);
       // X^{n0 + len} is the next checkpoint or, for the last segment, the
       // current state; neither holds rho, so that step reads its populations
       const SP endst = (sgi + 1 < (int64_t)c->ckpt.size()) ? sp(c->ckpt[sgi + 1]) : cur(c, c->cur);
       for (int64_t j = len - 1; j >= 0; --j) {
-        reverse_step(c, k, slot(j), (j + 1 == len) ? endst : slot(j + 1), n0 + j, *li, *lo);
+        reverse_step(c, k, slot(b, sgi, j), (j + 1 == len) ? endst : slot(b, sgi, j + 1), n0 + j, *li, *lo);
         std::swap(li, lo);
       }
       HIP_OR_FAIL(c, hipGetLastError());
+      if (sgi > 0) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->ev_done[1 - b], 0));
     }
     hipLaunchKernelGGL(gpf::k_grad_slices, dim3(gpf::GA), dim3(gpf::ADJ_BLOCK), 0, c->stream,
                        static_cast<const double*>(c->t_part.ptr), nparts, static_cast<double*>(c->t_slices.ptr));
@@ -863,10 +894,24 @@ void free_all(gpf_ctx* c) {
     dev_release(c, s.f);
     dev_release(c, s.dr);
   };
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+    c->side = nullptr;
+  }
   for (auto& s : c->ckpt) rel(s);
-  for (auto& s : c->tape) rel(s);
   c->ckpt.clear();
-  c->tape.clear();
+  for (int b = 0; b < 2; ++b) {
+    for (auto& s : c->tape[b]) rel(s);
+    c->tape[b].clear();
+    dev_release(c, c->tape_f[b][0]);
+    dev_release(c, c->tape_f[b][1]);
+  }
+  for (int b = 0; b < 2; ++b) {
+    if (c->ev_free[b]) (void)hipEventDestroy(c->ev_free[b]);
+    if (c->ev_done[b]) (void)hipEventDestroy(c->ev_done[b]);
+    c->ev_free[b] = c->ev_done[b] = nullptr;
+  }
   rel(c->lam[0]);
   rel(c->lam[1]);
   dev_release(c, c->t_phil);
@@ -879,8 +924,6 @@ void free_all(gpf_ctx* c) {
   dev_release(c, c->t_fflag);
   dev_release(c, c->t_fbuf);
   dev_release(c, c->t_cbuf);
-  dev_release(c, c->tape_f[0]);
-  dev_release(c, c->tape_f[1]);
 }
 
 int set_named(gpf_ctx* c, gpf_params& p, const char* name, double v) {
@@ -1060,10 +1103,11 @@ int gpf_record(gpf_ctx* c, int64_t checkpoint_every) {
   };
   for (auto& s : c->ckpt) rel(s);
   c->ckpt.clear();
-  if ((int64_t)c->tape.size() > checkpoint_every) {
-    for (auto& s : c->tape) rel(s);
-    c->tape.clear();
-  }
+  for (int b = 0; b < 2; ++b)
+    if ((int64_t)c->tape[b].size() > checkpoint_every) {
+      for (auto& s : c->tape[b]) rel(s);
+      c->tape[b].clear();
+    }
   c->rec_every = checkpoint_every;
   c->rec_start = c->step;
   c->have_adjoint = false;
