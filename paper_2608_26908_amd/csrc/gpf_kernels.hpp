@@ -36,7 +36,10 @@ __device__ __forceinline__ R pull_f(const KP<R>& p, const R* __restrict__ fin, i
         in = false;
     }
   }
-  if (in) return fin[k * p.cells + (int64_t)src[2] * p.sz + (int64_t)src[1] * p.sy + src[0]];
+  // each post-collision value is pulled once per step: a streaming
+  // (nontemporal) load, as the stores of the new state are streaming stores
+  if (in)
+    return __builtin_nontemporal_load(&fin[k * p.cells + (int64_t)src[2] * p.sz + (int64_t)src[1] * p.sy + src[0]]);
   R val = fin[Lat<Q>::opp(k) * p.cells + P];
   if (L::c(k, 1) < 0 && !p.per[1] && y - L::c(k, 1) >= p.n[1])
     val += R(6) * p.w[k] * p.rho0 * R(L::c(k, 0)) * p.lid_u;
@@ -326,7 +329,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
     mn[NC - 1] = mun[0][NC - 1] + (-a21 * Dl[0] + a11 * Dl[NC - 1]) / det;
   }
 #pragma unroll
-  for (int i = 0; i < NC; ++i) mu_out[i * p.cells + P] = mn[i];
+  for (int i = 0; i < NC; ++i) __builtin_nontemporal_store(mn[i], &mu_out[i * p.cells + P]);
 
   // ---- LBM: pull streaming of the previous post-collision populations ----
   R f[L::Q];
@@ -405,10 +408,10 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
     }
     const R feq = p.w[k] * (dr + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
     const R S = pref * p.w[k] * (R(3) * (cF - uF) + R(9) * cu * cF);
-    fout[k * p.cells + P] = f[k] - (f[k] - feq) / p.tau_lb + S;
+    __builtin_nontemporal_store(f[k] - (f[k] - feq) / p.tau_lb + S, &fout[k * p.cells + P]);
   }
 #pragma unroll
-  for (int a = 0; a < D; ++a) u_out[a * p.cells + P] = u[a];
+  for (int a = 0; a < D; ++a) __builtin_nontemporal_store(u[a], &u_out[a * p.cells + P]);
 }
 
 // coordinate along one axis of a tile-halo cell: periodic axes wrap, walls
@@ -507,7 +510,7 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
     phi_from_stencil<D, N, NC, R>(p, v, mu, xq, yq, z, tshift, res);
     const int64_t P = (int64_t)z * p.sz + (int64_t)yq * p.sy + xq;
 #pragma unroll
-    for (int q = 0; q < N; ++q) phi_out[q * p.cells + P] = res[q];
+    for (int q = 0; q < N; ++q) __builtin_nontemporal_store(res[q], &phi_out[q * p.cells + P]);
   };
 
   if (D == 2) {
