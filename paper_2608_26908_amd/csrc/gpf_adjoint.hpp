@@ -23,11 +23,25 @@ namespace gpf {
 enum { G_DELTA = 0, G_TAU = 1, G_D0 = 2, G_D1 = 3, G_GB0 = 4, G_GB1 = 5, NG = 6 };
 constexpr int ADJ_BLOCK = 256;
 
-__device__ __forceinline__ void cell_coords(const int64_t P, const int64_t sy, const int64_t sz,
-                                            const int nx, const int ny, int& x, int& y, int& z) {
-  x = (int)(P % nx);
-  y = (int)((P / sy) % ny);
-  z = (int)(P / sz);
+// Cell of a thread.  Work-groups are dealt to the 8 XCDs round-robin
+// (work-group b runs on XCD b mod 8); the grid is laid out so that XCD k owns
+// the rows [k ny / 8, (k + 1) ny / 8) of every plane and walks them plane by
+// plane.  A cell's neighbours in y and z are then, except at a slab edge,
+// read through the same L2, while all eight XCDs stream through the same
+// planes.  False for the padding slots at the end of an XCD's range.
+__device__ __forceinline__ bool adj_cell(const int (&n)[3], int64_t sy, int64_t sz, int64_t& P, int& x,
+                                         int& y, int& z) {
+  const unsigned k = blockIdx.x % 8u, i = blockIdx.x / 8u;
+  const int y0 = (int)(((int64_t)k * n[1]) / 8);
+  const unsigned h = (unsigned)((int)(((int64_t)(k + 1) * n[1]) / 8) - y0);
+  const unsigned s = i * (unsigned)ADJ_BLOCK + threadIdx.x;
+  if (s >= (unsigned)n[0] * h * (unsigned)n[2]) return false;
+  x = (int)(s % (unsigned)n[0]);
+  const unsigned r = s / (unsigned)n[0];
+  y = y0 + (int)(r % h);
+  z = (int)(r / h);
+  P = (int64_t)z * sz + (int64_t)y * sy + x;
+  return true;
 }
 
 // Per-block FP64 partial sums of the NG parameter derivatives, in a fixed
@@ -114,11 +128,10 @@ k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const 
           const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
           R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
   using L = Lat<Q>;
-  const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
-  if (P < p.cells) {
-    int x, y, z;
-    cell_coords(P, p.sy, p.sz, p.n[0], p.n[1], x, y, z);
+  int64_t P;
+  int x, y, z;
+  if (adj_cell(p.n, p.sy, p.sz, P, x, y, z)) {
     R f[TAPE ? 1 : L::Q], ob[L::Q];
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
@@ -490,11 +503,10 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
             const R* __restrict__ w, const R* __restrict__ lphi1, const R* __restrict__ t_phil,
             R* __restrict__ lphi0, R* __restrict__ lmu0, R* __restrict__ lu0, R* __restrict__ rbar,
             uint8_t* __restrict__ rflag, R tshift, double* __restrict__ part) {
-  const int64_t P = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
-  if (P < p.cells) {
-    int x, y, z;
-    cell_coords(P, p.sy, p.sz, p.n[0], p.n[1], x, y, z);
+  int64_t P;
+  int x, y, z;
+  if (adj_cell(p.n, p.sy, p.sz, P, x, y, z)) {
     R mubf[NC], Ubf[D], p1bf[N], p0bf[N];
     mu_adj_cell<D, N, NC, R>(p, P, x, y, z, phi0, phi1, mu0, mu1, u0, w, mubf, Ubf, p1bf, p0bf, gpart);
 #pragma unroll
@@ -809,11 +821,10 @@ k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
           const uint8_t* __restrict__ rflag, R* __restrict__ fbuf, uint8_t* __restrict__ fflag,
           R* __restrict__ cbuf, double* __restrict__ part) {
   constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
-  const int64_t L = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
-  if (L < p.cells) {
-    int lc[3];
-    cell_coords(L, p.sy, p.sz, p.n[0], p.n[1], lc[0], lc[1], lc[2]);
+  int64_t L;
+  int lc[3];
+  if (adj_cell(p.n, p.sy, p.sz, L, lc[0], lc[1], lc[2])) {
     const int Lc[3] = {lc[0], lc[1], lc[2]};
     R rl[N];
 #pragma unroll
@@ -891,10 +902,9 @@ __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
            const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf, R* __restrict__ lphi0) {
   constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
-  const int64_t X = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
-  if (X >= p.cells) return;
+  int64_t X;
   int xc[3];
-  cell_coords(X, p.sy, p.sz, p.n[0], p.n[1], xc[0], xc[1], xc[2]);
+  if (!adj_cell(p.n, p.sy, p.sz, X, xc[0], xc[1], xc[2])) return;
   // every role offset, and every face's other cell, lies in the 9/19-point
   // neighbourhood (at most two non-zero components), so the 3D corners are skipped
   bool any = false;

@@ -224,6 +224,10 @@ struct Ops {
 };
 
 inline unsigned lin_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// grid of the adjoint kernels: one slab of ceil(ny / 8) rows per XCD (gpf::adj_cell)
+inline unsigned adj_blocks(const int64_t (&n)[3]) {
+  return 8u * lin_blocks(n[0] * ((n[1] + 7) / 8) * n[2], gpf::ADJ_BLOCK);
+}
 
 // z-marching launch shape: 64 x GPF_TILE_Y tiles; each block of k_phi_z walks
 // GPF_ZCHUNK_PHI planes, each of k_mulbm_z GPF_ZCHUNK_MU (best measured of
@@ -532,7 +536,7 @@ struct Impl {
   // one reverse step: lam_in = adjoint of X^{n+1} -> lam_out = adjoint of X^n
   static void reverse_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, int64_t n,
                            StateBuf& li, StateBuf& lo) {
-    const unsigned nb = lin_blocks(c->cells, gpf::ADJ_BLOCK);
+    const unsigned nb = adj_blocks(c->n);
     double* part = static_cast<double*>(c->t_part.ptr);
     const int64_t pstride = (int64_t)nb * gpf::NG;
     const dim3 g(nb), b(gpf::ADJ_BLOCK);
@@ -560,11 +564,13 @@ struct Impl {
     const int64_t total = c->step - c->rec_start;
     if (K <= 0 || total <= 0 || c->ckpt.empty())
       return fail(c, GPF_ERR_STATE, "nothing recorded: call gpf_record before stepping");
+    if (c->n[0] * ((c->n[1] + 7) / 8) * c->n[2] >= ((int64_t)1 << 31))
+      return fail(c, GPF_ERR_UNSUPPORTED, "grid too large for the adjoint's 32-bit cell slots");
     const size_t cs = (size_t)c->cells * sizeof(R);
     int rc = GPF_OK;
     if (!c->lam[0].phi.ptr) {
       for (int i = 0; i < 2 && !rc; ++i) rc = alloc_state(c, c->lam[i]);
-      const unsigned nb = lin_blocks(c->cells, gpf::ADJ_BLOCK);
+      const unsigned nb = adj_blocks(c->n);
       if (!rc) rc = dev_alloc(c, c->t_phil, cs);
       if (!rc) rc = dev_alloc(c, c->t_w, NC * cs);
       if (!rc) rc = dev_alloc(c, c->t_rbar, N * cs);
@@ -613,7 +619,7 @@ struct Impl {
     hipLaunchKernelGGL((gpf::k_fill<double>), dim3(1), dim3(gpf::NG), 0, c->stream,
                        static_cast<double*>(c->t_acc.ptr), (int64_t)gpf::NG, 0.0);
     // per-block running sums of the parameter derivatives over the sweep
-    const int64_t nparts = (int64_t)3 * lin_blocks(c->cells, gpf::ADJ_BLOCK);
+    const int64_t nparts = (int64_t)3 * adj_blocks(c->n);
     hipLaunchKernelGGL((gpf::k_fill<double>), dim3(lin_blocks(nparts * gpf::NG, 256)), dim3(256), 0, c->stream,
                        static_cast<double*>(c->t_part.ptr), nparts * gpf::NG, 0.0);
     // slot j of segment sg in tape b holds X^{n0 + j} (slot 0 is the
