@@ -218,12 +218,19 @@ int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
  * GPF_ERR_UNSUPPORTED (shrinkage force on: eta != 0, or a moving frame),
  * GPF_ERR_NOMEM.
  *
+ * gpf_adjoint_device: gpf_adjoint with dL/dphi in device memory (FP64,
+ * same count and layout, e.g. a loss gradient computed on the GPU), read on
+ * the library's stream; the caller keeps ownership and must not change it
+ * before the call returns.  Same errors.
+ *
  * gpf_adjoint_state: after gpf_adjoint, dL/d(initial recorded state) for
  * GPF_PHI, GPF_MU, GPF_U (velocity of the step before) or GPF_F (the
  * populations after streaming), FP64, components * cells values. */
 int gpf_record(gpf_ctx* ctx, int64_t checkpoint_every);
 int gpf_adjoint(gpf_ctx* ctx, const double* dL_dphi, size_t count, const char* const* names,
                 int32_t n_names, double* grads_out);
+int gpf_adjoint_device(gpf_ctx* ctx, const void* dev_dL_dphi, size_t count, const char* const* names,
+                       int32_t n_names, double* grads_out);
 int gpf_adjoint_state(gpf_ctx* ctx, int32_t field, double* host_dst, size_t count);
 
 /* Step counter n (it sets the time of the pulled temperature field).  The

@@ -218,7 +218,7 @@ struct Ops {
   int (*write)(gpf_ctx*, int);          // from scratch
   int (*reduce)(gpf_ctx*, int, double*);
   int (*read_native)(gpf_ctx*, int, void*);
-  int (*adjoint)(gpf_ctx*, const double*, double*);
+  int (*adjoint)(gpf_ctx*, const double*, bool, double*);  // seed, seed in device memory, grads
   int (*copy_state)(gpf_ctx*, const StateBuf&, const StateBuf&);
   int (*lam_read)(gpf_ctx*, int, double*);
 };
@@ -558,8 +558,9 @@ struct Impl {
                        P(c->t_cbuf), P(lo.phi));
   }
 
-  // seed: dL/dphi at the current (final) state, FP64 host, N * cells values
-  static int adjoint(gpf_ctx* c, const double* seed, double* grads) {
+  // seed: dL/dphi at the current (final) state, FP64, N * cells values, in
+  // host memory or (seed_on_device) device memory
+  static int adjoint(gpf_ctx* c, const double* seed, bool seed_on_device, double* grads) {
     const int64_t K = c->rec_every;
     const int64_t total = c->step - c->rec_start;
     if (K <= 0 || total <= 0 || c->ckpt.empty())
@@ -609,10 +610,12 @@ struct Impl {
     // lam^N = (seed, 0, 0, 0)
     StateBuf* li = &c->lam[0];
     StateBuf* lo = &c->lam[1];
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->scratch.ptr, seed, (size_t)N * c->cells * sizeof(double),
-                                  hipMemcpyHostToDevice, c->stream));
+    if (!seed_on_device)
+      HIP_OR_FAIL(c, hipMemcpyAsync(c->scratch.ptr, seed, (size_t)N * c->cells * sizeof(double),
+                                    hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL((gpf::k_from_double<R>), dim3(lin_blocks(N * c->cells, 256)), dim3(256), 0,
-                       c->stream, static_cast<const double*>(c->scratch.ptr), P(li->phi), N * c->cells);
+                       c->stream, seed_on_device ? seed : static_cast<const double*>(c->scratch.ptr), P(li->phi),
+                       N * c->cells);
     fill(c, li->mu, NC * c->cells);
     fill(c, li->u, D * c->cells);
     fill(c, li->f, Q * c->cells);
@@ -1146,8 +1149,9 @@ static int grad_slot(const char* name) {
   return -1;
 }
 
-int gpf_adjoint(gpf_ctx* c, const double* dL_dphi, size_t count, const char* const* names,
-                int32_t n_names, double* grads_out) {
+namespace {
+int adjoint_entry(gpf_ctx* c, const double* dL_dphi, bool on_device, size_t count, const char* const* names,
+                  int32_t n_names, double* grads_out) {
   if (!c || !dL_dphi || (n_names > 0 && (!names || !grads_out)) || n_names < 0) return GPF_ERR_ARG;
   if (count != (size_t)c->N * (size_t)c->cells)
     return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, (size_t)c->N * (size_t)c->cells);
@@ -1163,10 +1167,21 @@ int gpf_adjoint(gpf_ctx* c, const double* dL_dphi, size_t count, const char* con
     if (slots[i] < 0) return fail(c, GPF_ERR_ARG, "unknown parameter '%s'", names[i] ? names[i] : "(null)");
   }
   double g[gpf::NG];
-  int rc = c->ops->adjoint(c, dL_dphi, g);
+  int rc = c->ops->adjoint(c, dL_dphi, on_device, g);
   if (rc) return rc;
   for (int i = 0; i < n_names; ++i) grads_out[i] = g[slots[i]];
   return GPF_OK;
+}
+}  // namespace
+
+int gpf_adjoint(gpf_ctx* c, const double* dL_dphi, size_t count, const char* const* names,
+                int32_t n_names, double* grads_out) {
+  return adjoint_entry(c, dL_dphi, false, count, names, n_names, grads_out);
+}
+
+int gpf_adjoint_device(gpf_ctx* c, const void* dev_dL_dphi, size_t count, const char* const* names,
+                       int32_t n_names, double* grads_out) {
+  return adjoint_entry(c, static_cast<const double*>(dev_dL_dphi), true, count, names, n_names, grads_out);
 }
 
 int gpf_adjoint_state(gpf_ctx* c, int32_t field, double* host_dst, size_t count) {

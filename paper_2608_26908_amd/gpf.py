@@ -97,6 +97,7 @@ def lib():
         L.gpf_destroy.argtypes = [vp]
         L.gpf_record.argtypes = [vp, i64]
         L.gpf_adjoint.argtypes = [vp, dp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_char_p), i32, dp]
+        L.gpf_adjoint_device.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_char_p), i32, dp]
         L.gpf_adjoint_state.argtypes = [vp, i32, dp, ctypes.c_size_t]
         _lib = L
     return _lib
@@ -294,13 +295,20 @@ class Sim:
 
     def adjoint(self, dL_dphi, names):
         """FP64 dL/dp for the named parameters, given dL/dphi at the current
-        state; the adjoint of the recorded initial state is then available
-        from adjoint_state()."""
-        seed = np.ascontiguousarray(dL_dphi, dtype=np.float64).ravel()
+        state (a host array, or a GPU tensor: then gpf_adjoint_device reads
+        it in place); the adjoint of the recorded initial state is then
+        available from adjoint_state()."""
         arr = (ctypes.c_char_p * len(names))(*[n.encode() for n in names])
         out = (ctypes.c_double * max(1, len(names)))()
-        self._check(lib().gpf_adjoint(self._h, seed.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                      seed.size, arr, len(names), out))
+        if getattr(dL_dphi, "is_cuda", False):
+            import torch
+            seed = dL_dphi.detach().to(torch.float64).contiguous()
+            self._check(lib().gpf_adjoint_device(self._h, ctypes.c_void_p(seed.data_ptr()), seed.numel(),
+                                                 arr, len(names), out))
+        else:
+            seed = np.ascontiguousarray(dL_dphi, dtype=np.float64).ravel()
+            self._check(lib().gpf_adjoint(self._h, seed.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          seed.size, arr, len(names), out))
         return np.array(out[: len(names)])
 
     def adjoint_state(self, field):
@@ -333,7 +341,7 @@ def _autograd_function():
 
         @staticmethod
         def backward(ctx, grad_phi):
-            g = ctx.sim.adjoint(grad_phi.detach().double().cpu().numpy(), ctx.names)
+            g = ctx.sim.adjoint(grad_phi, ctx.names)
             return torch.tensor(g, dtype=torch.float64), None, None, None, None, None
 
     return GPFRun

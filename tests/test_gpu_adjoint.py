@@ -85,6 +85,8 @@ def test_ternary_two_solute_gradients_fp64(oracle):
 
 
 def test_adjoint_leaves_forward_state_and_is_deterministic():
+    """Two sweeps give bitwise the same gradients, host or device seed, and
+    the forward state is left as it was."""
     from paper_2608_26908_amd.gpf import Sim
     cfg = scaled("adjoint2d", [32, 32], init_radius=5.0)
     g = Sim(cfg, precision="fp32")
@@ -95,6 +97,10 @@ def test_adjoint_leaves_forward_state_and_is_deterministic():
     a = g.adjoint(seed, ["delta", "tau_pf", "D", "gbeta"])
     b = g.adjoint(seed, ["delta", "tau_pf", "D", "gbeta"])
     assert np.array_equal(a, b)
+    # the seed in device memory (gpf_adjoint_device) gives the same result
+    import torch
+    c = g.adjoint(torch.tensor(seed, dtype=torch.float64, device="cuda"), ["delta", "tau_pf", "D", "gbeta"])
+    assert np.array_equal(a, c)
     assert np.array_equal(g.read("phi"), phi)
     assert g.step_index == 12
 
