@@ -200,7 +200,10 @@ int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
  * steps (device memory: (N + nc + dim + Q) * cells values per checkpoint;
  * gpf_adjoint adds a tape of checkpoint_every - 1 states of
  * (N + nc + dim + 1) * cells values, two population buffers and the adjoint
- * state).
+ * state).  Checkpoint m belongs to step (start + m checkpoint_every): a state
+ * restored to an earlier step and stepped again overwrites the later ones;
+ * gpf_step fails with GPF_ERR_STATE at a checkpoint step before the start of
+ * the recording or past the next checkpoint in sequence.
  * Errors: GPF_ERR_ARG (checkpoint_every < 1), GPF_ERR_NOMEM.
  *
  * gpf_adjoint: given dL/dphi at the current state (FP64 host array of

@@ -11,6 +11,8 @@
 //               projection and local phase-field terms         Rbar, d tau
 //   k_adj_vjp   reverse of each face flux / cell term, once  -> per-role contributions, d delta
 //   k_adj_phi2  gather of those contributions               -> lam phi^n
+// k_adj_lbm of step n - 1 does not read lam phi^n, so k_adj_phi2_lbm runs it
+// in the same launch as the gather of step n (used on small grids).
 // Every kernel gathers into the cells it owns: no atomics, deterministic.
 // Parameter derivatives are reduced per block in FP64 and summed in a fixed
 // order.  Hessian-vector products of the gradient energy come from forward
@@ -122,16 +124,16 @@ __device__ __forceinline__ R d2h(const R (&ph)[N], int b, int a, int g) {
 // is the step's own output, so f is not read; otherwise both are recomputed
 // from the pulled f (the last step of a checkpoint segment).
 template <int D, int Q, int N, int NC, class R, bool TAPE>
-__global__ void __launch_bounds__(ADJ_BLOCK)
-k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
-          const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
-          const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
-          R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
+__device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, const int x, const int y,
+                                             const int z, const R* __restrict__ fst,
+                                             const R* __restrict__ dr_t, const R* __restrict__ u1,
+                                             const R* __restrict__ phi1, const R* __restrict__ mu1,
+                                             const R* __restrict__ lf1, const R* __restrict__ lu1,
+                                             const R* __restrict__ lmu1, R* __restrict__ lf0,
+                                             R* __restrict__ t_phil, R* __restrict__ w,
+                                             R* __restrict__ lmu0, double (&gpart)[NG]) {
   using L = Lat<Q>;
-  double gpart[NG] = {0, 0, 0, 0, 0, 0};
-  int64_t P;
-  int x, y, z;
-  if (adj_cell(p.n, p.sy, p.sz, P, x, y, z)) {
+  {
     R f[TAPE ? 1 : L::Q], ob[L::Q];
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
@@ -306,6 +308,20 @@ k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const 
       w[p.cells + P] = (-a12 * mt[0] + a11 * mt[NC - 1]) / det;
     }
   }
+}
+
+template <int D, int Q, int N, int NC, class R, bool TAPE>
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
+          const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
+          const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
+          R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
+  double gpart[NG] = {0, 0, 0, 0, 0, 0};
+  int64_t P;
+  int x, y, z;
+  if (adj_cell(p.n, p.sy, p.sz, P, x, y, z))
+    adj_lbm_cell<D, Q, N, NC, R, TAPE>(p, P, x, y, z, fst, dr_t, u1, phi1, mu1, lf1, lu1, lmu1, lf0, t_phil, w,
+                                       lmu0, gpart);
   block_partials(gpart, part);
 }
 
@@ -898,13 +914,11 @@ __device__ __forceinline__ int face_role_off(int a, int r, int e) {
 // 5b. Gather: lam phi^n(X) += every stored contribution whose role cell is X.
 // Cells with no flagged seed in their 9/19-point neighbourhood return at once.
 template <int D, int N, int NC, class R>
-__global__ void __launch_bounds__(ADJ_BLOCK)
-k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
-           const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf, R* __restrict__ lphi0) {
+__device__ __forceinline__ void adj_phi2_cell(const KP<R>& p, const int64_t X, const int (&xc)[3],
+                                              const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
+                                              const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf,
+                                              R* __restrict__ lphi0) {
   constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
-  int64_t X;
-  int xc[3];
-  if (!adj_cell(p.n, p.sy, p.sz, X, xc[0], xc[1], xc[2])) return;
   // every role offset, and every face's other cell, lies in the 9/19-point
   // neighbourhood (at most two non-zero components), so the 3D corners are skipped
   bool any = false;
@@ -1023,6 +1037,39 @@ k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbu
   }
 #pragma unroll
   for (int b = 0; b < N; ++b) lphi0[b * p.cells + X] += acc[b];
+}
+
+template <int D, int N, int NC, class R>
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
+           const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf, R* __restrict__ lphi0) {
+  int64_t X;
+  int xc[3];
+  if (adj_cell(p.n, p.sy, p.sz, X, xc[0], xc[1], xc[2]))
+    adj_phi2_cell<D, N, NC, R>(p, X, xc, rflag, fbuf, fflag, cbuf, lphi0);
+}
+
+// 5b + 1 of the step before.  The streaming/collision reverse of step n - 1
+// reads the adjoint populations, mu and U of step n, which k_adj_lbm and
+// k_adj_muphi of step n wrote, but not lam phi^n: so it runs in the same
+// launch as the gather of step n (one kernel boundary less per step).
+template <int D, int Q, int N, int NC, class R, bool TAPE>
+__global__ void __launch_bounds__(ADJ_BLOCK)
+k_adj_phi2_lbm(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
+               const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf, R* __restrict__ lphi0,
+               const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
+               const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
+               const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
+               R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
+  double gpart[NG] = {0, 0, 0, 0, 0, 0};
+  int64_t P;
+  int xc[3];
+  if (adj_cell(p.n, p.sy, p.sz, P, xc[0], xc[1], xc[2])) {
+    adj_phi2_cell<D, N, NC, R>(p, P, xc, rflag, fbuf, fflag, cbuf, lphi0);
+    adj_lbm_cell<D, Q, N, NC, R, TAPE>(p, P, xc[0], xc[1], xc[2], fst, dr_t, u1, phi1, mu1, lf1, lu1, lmu1, lf0,
+                                       t_phil, w, lmu0, gpart);
+  }
+  block_partials(gpart, part);
 }
 
 // Sum the per-block running sums of the reverse sweep in a fixed order: each

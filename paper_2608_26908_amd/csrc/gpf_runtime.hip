@@ -517,11 +517,20 @@ struct Impl {
     HIP_OR_FAIL(c, hipMemcpyAsync(dst.f.ptr, src.f.ptr, dst.f.bytes, hipMemcpyDeviceToDevice, c->stream));
     return GPF_OK;
   }
+  // checkpoint m = (step - rec_start) / rec_every of the recording; a state
+  // restored to an earlier step and stepped again overwrites the later ones
   static int save_ckpt(gpf_ctx* c) {
-    StateBuf s;
-    int rc = alloc_state(c, s);
-    if (rc) return rc;
-    c->ckpt.push_back(s);
+    const int64_t m = (c->step - c->rec_start) / c->rec_every;
+    if (c->step < c->rec_start || m > (int64_t)c->ckpt.size())
+      return fail(c, GPF_ERR_STATE, "step %lld is outside the recording started at step %lld",
+                  (long long)c->step, (long long)c->rec_start);
+    if (m == (int64_t)c->ckpt.size()) {
+      StateBuf s;
+      int rc = alloc_state(c, s);
+      if (rc) return rc;
+      c->ckpt.push_back(s);
+    }
+    StateBuf& s = c->ckpt[m];
     StateBuf cur_s;
     cur_s.phi = c->phi[c->cur];
     cur_s.mu = c->mu[c->cur];
@@ -533,29 +542,60 @@ struct Impl {
     hipLaunchKernelGGL((gpf::k_fill<R>), dim3(lin_blocks(n, 256)), dim3(256), 0, c->stream, P(b), n, R(0));
   }
 
-  // one reverse step: lam_in = adjoint of X^{n+1} -> lam_out = adjoint of X^n
-  static void reverse_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, int64_t n,
-                           StateBuf& li, StateBuf& lo) {
+  // Reverse of step n (X^n -> X^{n+1}): lam_in = adjoint of X^{n+1}, lam_out =
+  // adjoint of X^n.  Four stages, each a kernel boundary: the LBM reverse,
+  // the mu / phi-local reverse, the flux VJPs, their gather.  On small grids
+  // the gather of step n and the LBM reverse of step n - 1 share a launch.
+  struct AdjLaunch {
+    dim3 g, b;
+    double* part;
+    int64_t pstride;
+    uint8_t *rflag, *fflag;
+  };
+  static AdjLaunch adj_launch(gpf_ctx* c) {
     const unsigned nb = adj_blocks(c->n);
-    double* part = static_cast<double*>(c->t_part.ptr);
-    const int64_t pstride = (int64_t)nb * gpf::NG;
-    const dim3 g(nb), b(gpf::ADJ_BLOCK);
+    return {dim3(nb), dim3(gpf::ADJ_BLOCK), static_cast<double*>(c->t_part.ptr), (int64_t)nb * gpf::NG,
+            static_cast<uint8_t*>(c->t_rflag.ptr), static_cast<uint8_t*>(c->t_fflag.ptr)};
+  }
+  static void adj_lbm(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, StateBuf& li, StateBuf& lo) {
+    const AdjLaunch a = adj_launch(c);
     if (x1.dr)
-      hipLaunchKernelGGL((gpf::k_adj_lbm<D, Q, N, NC, R, true>), g, b, 0, c->stream, k, x0.f, x1.dr, x1.u, x1.phi,
-                         x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu), part);
-    else
-      hipLaunchKernelGGL((gpf::k_adj_lbm<D, Q, N, NC, R, false>), g, b, 0, c->stream, k, x0.f, x1.dr, x1.u,
+      hipLaunchKernelGGL((gpf::k_adj_lbm<D, Q, N, NC, R, true>), a.g, a.b, 0, c->stream, k, x0.f, x1.dr, x1.u,
                          x1.phi, x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu),
-                         part);
-    uint8_t* rflag = static_cast<uint8_t*>(c->t_rflag.ptr);
-    uint8_t* fflag = static_cast<uint8_t*>(c->t_fflag.ptr);
-    hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R>), g, b, 0, c->stream, k, x0.phi, x1.phi,
+                         a.part);
+    else
+      hipLaunchKernelGGL((gpf::k_adj_lbm<D, Q, N, NC, R, false>), a.g, a.b, 0, c->stream, k, x0.f, x1.dr, x1.u,
+                         x1.phi, x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu),
+                         a.part);
+  }
+  static void adj_muphi_vjp(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, int64_t n,
+                            StateBuf& li, StateBuf& lo) {
+    const AdjLaunch a = adj_launch(c);
+    hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R>), a.g, a.b, 0, c->stream, k, x0.phi, x1.phi,
                        x0.mu, x1.mu, x0.u, P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
-                       P(lo.mu), P(lo.u), P(c->t_rbar), rflag, (R)tshift(c, n), part + pstride);
-    hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), g, b, 0, c->stream, k, x0.phi, P(c->t_rbar), rflag,
-                       P(c->t_fbuf), fflag, P(c->t_cbuf), part + 2 * pstride);
-    hipLaunchKernelGGL((gpf::k_adj_phi2<D, N, NC, R>), g, b, 0, c->stream, k, rflag, P(c->t_fbuf), fflag,
+                       P(lo.mu), P(lo.u), P(c->t_rbar), a.rflag, (R)tshift(c, n), a.part + a.pstride);
+    hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), a.g, a.b, 0, c->stream, k, x0.phi, P(c->t_rbar), a.rflag,
+                       P(c->t_fbuf), a.fflag, P(c->t_cbuf), a.part + 2 * a.pstride);
+  }
+  // gather of step n into lo.phi alone (the last reverse step)
+  static void adj_phi2(gpf_ctx* c, const gpf::KP<R>& k, StateBuf& lo) {
+    const AdjLaunch a = adj_launch(c);
+    hipLaunchKernelGGL((gpf::k_adj_phi2<D, N, NC, R>), a.g, a.b, 0, c->stream, k, a.rflag, P(c->t_fbuf), a.fflag,
                        P(c->t_cbuf), P(lo.phi));
+  }
+  // gather of step n into lo.phi, and the LBM reverse of step n - 1 (states
+  // x0 = X^{n-1}, x1 = X^n) from lo (the adjoint of X^n) into li
+  static void adj_phi2_lbm(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, StateBuf& lo,
+                           StateBuf& li) {
+    const AdjLaunch a = adj_launch(c);
+    if (x1.dr)
+      hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, true>), a.g, a.b, 0, c->stream, k, a.rflag,
+                         P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), x0.f, x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
+                         P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), a.part);
+    else
+      hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, false>), a.g, a.b, 0, c->stream, k, a.rflag,
+                         P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), x0.f, x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
+                         P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), a.part);
   }
 
   // seed: dL/dphi at the current (final) state, FP64, N * cells values, in
@@ -635,33 +675,64 @@ struct Impl {
       return s;
     };
     auto seg_len = [&](int64_t sg) { return std::min<int64_t>(K, total - sg * K); };
-    auto recompute = [&](int b, int64_t sg, hipStream_t st) {
-      const int64_t n0 = c->rec_start + sg * K;
-      for (int64_t j = 0; j < seg_len(sg) - 1; ++j)
-        launch_step(c, k, slot(b, sg, j), slot(b, sg, j + 1), (R)tshift(c, n0 + j), st, nullptr);
+    // step j of the recomputation of segment sg into tape b
+    auto recompute_step = [&](int b, int64_t sg, int64_t j, hipStream_t st) {
+      launch_step(c, k, slot(b, sg, j), slot(b, sg, j + 1), (R)tshift(c, c->rec_start + sg * K + j), st, nullptr);
     };
-    recompute(0, nseg - 1, c->stream);
-    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
-      const int b = (int)((nseg - 1 - sgi) & 1);
-      if (sgi > 0) {
-        // the previous segment goes into the other tape once the reverse of
-        // the segment that used it (already queued) is done
-        HIP_OR_FAIL(c, hipEventRecord(c->ev_free[1 - b], c->stream));
-        HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->ev_free[1 - b], 0));
-        recompute(1 - b, sgi - 1, c->side);
-        HIP_OR_FAIL(c, hipEventRecord(c->ev_done[1 - b], c->side));
+    auto tape_of = [&](int64_t sg) { return (int)((nseg - 1 - sg) & 1); };
+    // X^{rec_start + m}, m in [0, total]: the checkpoints every K steps, the
+    // current state at m = total (neither holds rho - rho0, so the LBM reverse
+    // of the step that ends there reads its populations), else slot m mod K
+    // of its segment's tape
+    auto state = [&](int64_t m) -> SP {
+      const int64_t sg = m / K, j = m % K;
+      if (j == 0 && sg < (int64_t)c->ckpt.size()) return sp(c->ckpt[sg]);
+      if (m == total) return cur(c, c->cur);
+      return slot(tape_of(sg), sg, j);
+    };
+    // The gather and the next LBM reverse share a launch on grids that do not
+    // fill the chip even at four waves per SIMD (256 CUs x 4 SIMDs x 4 x 64
+    // cells): there the kernels are latency-bound and a boundary costs more
+    // than the fused kernel's registers (121, against 67 for the gather alone).
+    const bool fuse = c->cells <= (int64_t)256 * 4 * 4 * 64;
+    for (int64_t j = 0; j < seg_len(nseg - 1) - 1; ++j) recompute_step(0, nseg - 1, j, c->stream);
+    adj_lbm(c, k, state(total - 1), state(total), *li, *lo);
+    int64_t nrec = 0, jr = 0;
+    for (int64_t m = total - 1; m >= 0; --m) {
+      const int64_t sg = m / K, j = m % K;
+      const int b = tape_of(sg);
+      if (m == total - 1 || j == K - 1) {
+        // first reverse step of segment sg: the previous segment goes into the
+        // other tape once everything that read that tape (already queued) is
+        // done; its steps are queued alternately with the reverse steps, so
+        // neither stream waits for the host to queue the other's work
+        nrec = (sg > 0) ? K - 1 : 0;
+        jr = 0;
+        if (sg > 0) {
+          HIP_OR_FAIL(c, hipEventRecord(c->ev_free[1 - b], c->stream));
+          HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->ev_free[1 - b], 0));
+        }
       }
-      const int64_t n0 = c->rec_start + sgi * K;
-      const int64_t len = seg_len(sgi);
-      // X^{n0 + len} is the next checkpoint or, for the last segment, the
-      // current state; neither holds rho, so that step reads its populations
-      const SP endst = (sgi + 1 < (int64_t)c->ckpt.size()) ? sp(c->ckpt[sgi + 1]) : cur(c, c->cur);
-      for (int64_t j = len - 1; j >= 0; --j) {
-        reverse_step(c, k, slot(b, sgi, j), (j + 1 == len) ? endst : slot(b, sgi, j + 1), n0 + j, *li, *lo);
-        std::swap(li, lo);
+      adj_muphi_vjp(c, k, state(m), state(m + 1), c->rec_start + m, *li, *lo);
+      if (jr < nrec) recompute_step(1 - b, sg - 1, jr++, c->side);
+      if (m > 0) {
+        if (j == 0) {
+          // step m - 1 lies in the previous segment: its tape must be complete
+          while (jr < nrec) recompute_step(1 - b, sg - 1, jr++, c->side);
+          HIP_OR_FAIL(c, hipEventRecord(c->ev_done[1 - b], c->side));
+          HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->ev_done[1 - b], 0));
+        }
+        if (fuse) {
+          adj_phi2_lbm(c, k, state(m - 1), state(m), *lo, *li);
+        } else {
+          adj_phi2(c, k, *lo);
+          adj_lbm(c, k, state(m - 1), state(m), *lo, *li);
+        }
+      } else {
+        adj_phi2(c, k, *lo);
       }
       HIP_OR_FAIL(c, hipGetLastError());
-      if (sgi > 0) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->ev_done[1 - b], 0));
+      std::swap(li, lo);
     }
     hipLaunchKernelGGL(gpf::k_grad_slices, dim3(gpf::GA), dim3(gpf::ADJ_BLOCK), 0, c->stream,
                        static_cast<const double*>(c->t_part.ptr), nparts, static_cast<double*>(c->t_slices.ptr));
