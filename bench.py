@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-drift", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the shrinkage, D3Q27, moving-frame and four-phase lines (profiling runs)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a kernel of known "
                          "traffic to calibrate the HBM byte counters of a profiler run)")
@@ -207,29 +209,31 @@ def main():
         print(f"# fp64: {r64['mlups']:.1f} MLUPS, {r64['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
 
-    # the shrinkage force of Eq. (shrinkage) on (rho_s / rho_l = 1.2): the same
-    # workload, extra arithmetic on values the kernel already holds
-    rs = run_gpu(workload(args.workload, eta=[0.2, 0.0, 0.0]), "fp32", min(args.steps, 100),
-                 args.warmup)
-    print(f"# fp32 with shrinkage: {rs['mlups']:.1f} MLUPS, {rs['ms_per_step']:.3f} ms/step",
-          file=sys.stderr, flush=True)
-    # the paper's own 3D lattice, D3Q27 (Table LBM_Schemes), on the same workload
+    rs = r27 = rf0 = rf1 = r4 = None
     c27 = workload(args.workload, lattice="D3Q27")
-    r27 = run_gpu(c27, "fp32", min(args.steps, 100), args.warmup)
-    print(f"# fp32 D3Q27: {r27['mlups']:.1f} MLUPS, {r27['ms_per_step']:.3f} ms/step", file=sys.stderr,
-          flush=True)
-    # the moving frame of Case 2 on the eutectic (1024 x 512): a front search
-    # every 100 steps (one synchronisation) and the shifts it triggers
-    e2 = workload("eutectic2d")
-    rf0 = run_gpu(e2, "fp32", 1000, 50)
-    rf1 = run_gpu(dict(e2, frame_every=100, frame_front=16), "fp32", 1000, 50)
-    print(f"# eutectic2d fp32: {rf0['mlups']:.1f} MLUPS, with the moving frame {rf1['mlups']:.1f}",
-          file=sys.stderr, flush=True)
-    # four phases (three solids and the liquid, Case 3), 192 x 192 x 384 D3Q19
     c4 = workload("eutectic4_3d")
-    r4 = run_gpu(c4, "fp32", min(args.steps, 100), args.warmup)
-    print(f"# fp32 four phases: {r4['mlups']:.1f} MLUPS, {r4['ms_per_step']:.3f} ms/step", file=sys.stderr,
-          flush=True)
+    if not args.no_extra:
+        # the shrinkage force of Eq. (shrinkage) on (rho_s / rho_l = 1.2): the same
+        # workload, extra arithmetic on values the kernel already holds
+        rs = run_gpu(workload(args.workload, eta=[0.2, 0.0, 0.0]), "fp32", min(args.steps, 100),
+                     args.warmup)
+        print(f"# fp32 with shrinkage: {rs['mlups']:.1f} MLUPS, {rs['ms_per_step']:.3f} ms/step",
+              file=sys.stderr, flush=True)
+        # the paper's own 3D lattice, D3Q27 (Table LBM_Schemes), on the same workload
+        r27 = run_gpu(c27, "fp32", min(args.steps, 100), args.warmup)
+        print(f"# fp32 D3Q27: {r27['mlups']:.1f} MLUPS, {r27['ms_per_step']:.3f} ms/step", file=sys.stderr,
+              flush=True)
+        # the moving frame of Case 2 on the eutectic (1024 x 512): a front search
+        # every 100 steps (one synchronisation) and the shifts it triggers
+        e2 = workload("eutectic2d")
+        rf0 = run_gpu(e2, "fp32", 1000, 50)
+        rf1 = run_gpu(dict(e2, frame_every=100, frame_front=16), "fp32", 1000, 50)
+        print(f"# eutectic2d fp32: {rf0['mlups']:.1f} MLUPS, with the moving frame {rf1['mlups']:.1f}",
+              file=sys.stderr, flush=True)
+        # four phases (three solids and the liquid, Case 3), 192 x 192 x 384 D3Q19
+        r4 = run_gpu(c4, "fp32", min(args.steps, 100), args.warmup)
+        print(f"# fp32 four phases: {r4['mlups']:.1f} MLUPS, {r4['ms_per_step']:.3f} ms/step", file=sys.stderr,
+              flush=True)
     copy_gbs = copy_bandwidth()
     print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     b32 = bytes_per_lup(cfg, 4)
@@ -263,25 +267,26 @@ def main():
                      "copy_GBps": round(copy_gbs, 1)},
         "kernels_ms": {"k_phi": round(r32["k_phi_ms"], 4), "k_mulbm": round(r32["k_mulbm_ms"], 4)},
     }
-    line["shrinkage"] = {"value": round(rs["mlups"], 2), "unit": "MLUPS", "eta": [0.2, 0.0, 0.0],
-                         "ms_per_step": round(rs["ms_per_step"], 4),
-                         "k_phi_ms": round(rs["k_phi_ms"], 4), "k_mulbm_ms": round(rs["k_mulbm_ms"], 4)}
-    line["moving_frame"] = {"workload": "eutectic2d 1024x512 FP32, front search every 100 steps, front kept at 16",
-                            "value": round(rf1["mlups"], 2), "unit": "MLUPS",
-                            "without_frame": round(rf0["mlups"], 2)}
-    b4 = bytes_per_lup(c4, 4)
-    line["four_phase"] = {"workload": "eutectic4_3d: 192x192x384 D3Q19, 4 phases, 2 solutes, FP32",
-                          "value": round(r4["mlups"], 2), "unit": "MLUPS",
-                          "ms_per_step": round(r4["ms_per_step"], 4), "k_phi_ms": round(r4["k_phi_ms"], 4),
-                          "k_mulbm_ms": round(r4["k_mulbm_ms"], 4), "bytes_per_lup": b4,
-                          "roofline_frac": round(b4 * r4["cells"] / (r4["k_mulbm_ms"] * 1e-3) / 1e9
-                                                 / HBM_PEAK_GBS, 4)}
-    b27 = bytes_per_lup(c27, 4)
-    line["d3q27"] = {"value": round(r27["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(r27["ms_per_step"], 4),
-                     "k_phi_ms": round(r27["k_phi_ms"], 4), "k_mulbm_ms": round(r27["k_mulbm_ms"], 4),
-                     "bytes_per_lup": b27,
-                     "roofline_frac": round(b27 * cells / (r27["k_mulbm_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "step_frac": round(b27 * cells / (r27["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if not args.no_extra:
+        line["shrinkage"] = {"value": round(rs["mlups"], 2), "unit": "MLUPS", "eta": [0.2, 0.0, 0.0],
+                             "ms_per_step": round(rs["ms_per_step"], 4),
+                             "k_phi_ms": round(rs["k_phi_ms"], 4), "k_mulbm_ms": round(rs["k_mulbm_ms"], 4)}
+        line["moving_frame"] = {"workload": "eutectic2d 1024x512 FP32, front search every 100 steps, front kept at 16",
+                                "value": round(rf1["mlups"], 2), "unit": "MLUPS",
+                                "without_frame": round(rf0["mlups"], 2)}
+        b4 = bytes_per_lup(c4, 4)
+        line["four_phase"] = {"workload": "eutectic4_3d: 192x192x384 D3Q19, 4 phases, 2 solutes, FP32",
+                              "value": round(r4["mlups"], 2), "unit": "MLUPS",
+                              "ms_per_step": round(r4["ms_per_step"], 4), "k_phi_ms": round(r4["k_phi_ms"], 4),
+                              "k_mulbm_ms": round(r4["k_mulbm_ms"], 4), "bytes_per_lup": b4,
+                              "roofline_frac": round(b4 * r4["cells"] / (r4["k_mulbm_ms"] * 1e-3) / 1e9
+                                                     / HBM_PEAK_GBS, 4)}
+        b27 = bytes_per_lup(c27, 4)
+        line["d3q27"] = {"value": round(r27["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(r27["ms_per_step"], 4),
+                         "k_phi_ms": round(r27["k_phi_ms"], 4), "k_mulbm_ms": round(r27["k_mulbm_ms"], 4),
+                         "bytes_per_lup": b27,
+                         "roofline_frac": round(b27 * cells / (r27["k_mulbm_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "step_frac": round(b27 * cells / (r27["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if r64:
         b64 = bytes_per_lup(cfg, 8)
         line["fp64"] = {"value": round(r64["mlups"], 2), "unit": "MLUPS",
