@@ -127,7 +127,7 @@ def solute_drift(cfg, precision, steps=10000):
     return float(np.max(np.abs(s1 - s0) / np.abs(s0)))
 
 
-def cpu_baseline(cfg, steps=2):
+def cpu_baseline(cfg, steps=7):
     """The FP64 oracle as it stands, on this host's cores, on a bounded
     sample of the same workload: the full grid, one untimed step, then
     `steps` timed steps."""
