@@ -307,6 +307,23 @@ def main():
                      "checkpoint every 25",
             **run_adjoint(e3, "fp32", 100, 25, ["D", "D1"]))
         print(f"# adjoint3d: ratio {line['adjoint3d']['ratio']}", file=sys.stderr, flush=True)
+    if not args.no_extra:
+        # every workload of the paper's configurations, FP32 and FP64 side by
+        # side: MLUPS and the step's fraction of the HBM roofline at its own
+        # algorithmic bytes per LUP
+        per = {}
+        for name, steps in (("dendrite2d", 2000), ("eutectic2d", 1000), ("dendrite3d", 50),
+                            ("adjoint2d", 2000), ("eutectic3d", 50)):
+            wc = workload(name)
+            row = {"grid": wc["n"], "phases": wc["N"], "solutes": wc["nc"]}
+            for prec, s in (("fp32", 4), ("fp64", 8)):
+                r = run_gpu(wc, prec, steps, max(10, steps // 10))
+                row[prec] = {"MLUPS": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                             "step_frac": round(bytes_per_lup(wc, s) * r["mlups"] * 1e6 / 1e9 / HBM_PEAK_GBS, 4)}
+            per[name] = row
+            print(f"# {name}: fp32 {row['fp32']['MLUPS']} MLUPS, fp64 {row['fp64']['MLUPS']} MLUPS",
+                  file=sys.stderr, flush=True)
+        line["configs"] = per
     if not args.no_drift:
         drift = {"dendrite3d_fp32": solute_drift(cfg, "fp32")}
         e2 = workload("eutectic2d")

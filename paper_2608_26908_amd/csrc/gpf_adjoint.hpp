@@ -518,7 +518,7 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
             const R* __restrict__ mu0, const R* __restrict__ mu1, const R* __restrict__ u0,
             const R* __restrict__ w, const R* __restrict__ lphi1, const R* __restrict__ t_phil,
             R* __restrict__ lphi0, R* __restrict__ lmu0, R* __restrict__ lu0, R* __restrict__ rbar,
-            uint8_t* __restrict__ rflag, R tshift, double* __restrict__ part) {
+            uint8_t* __restrict__ rflag, uint8_t* __restrict__ rowflag, R tshift, double* __restrict__ part) {
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
   int64_t P;
   int x, y, z;
@@ -627,6 +627,8 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
       nz = nz || (Rb[b] != R(0));
     }
     rflag[P] = nz ? 1 : 0;
+    // the (y, z) row holds a seed: every writer stores the same value
+    if (nz) rowflag[(int64_t)z * p.n[1] + y] = 1;
   }
   block_partials(gpart, part);
 }
@@ -913,12 +915,28 @@ __device__ __forceinline__ int face_role_off(int a, int r, int e) {
 
 // 5b. Gather: lam phi^n(X) += every stored contribution whose role cell is X.
 // Cells with no flagged seed in their 9/19-point neighbourhood return at once.
+// rowflag: per (y, z) row, 1 if a cell of the row holds a seed (written by
+// k_adj_muphi of this step); rowclear: the other step parity's row flags,
+// cleared here (one thread per row) for the next reverse step.
 template <int D, int N, int NC, class R>
 __device__ __forceinline__ void adj_phi2_cell(const KP<R>& p, const int64_t X, const int (&xc)[3],
                                               const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
                                               const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf,
-                                              R* __restrict__ lphi0) {
+                                              R* __restrict__ lphi0, const uint8_t* __restrict__ rowflag,
+                                              uint8_t* __restrict__ rowclear) {
   constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
+  if (xc[0] == 0) rowclear[(int64_t)xc[2] * p.n[1] + xc[1]] = 0;
+  // no seed in the 3 x 3 rows (y, z) around the cell: nothing to gather
+  bool row_any = false;
+#pragma unroll
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = nb_field(xc[1], dy, p.n[1], p.per[1]);
+      const int zz = (D == 3) ? nb_field(xc[2], dz, p.n[2], p.per[2]) : 0;
+      row_any = row_any | (rowflag[(int64_t)zz * p.n[1] + yy] != 0);
+    }
+  if (!row_any) return;
   // every role offset, and every face's other cell, lies in the 9/19-point
   // neighbourhood (at most two non-zero components), so the 3D corners are skipped
   bool any = false;
@@ -1042,11 +1060,12 @@ __device__ __forceinline__ void adj_phi2_cell(const KP<R>& p, const int64_t X, c
 template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
-           const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf, R* __restrict__ lphi0) {
+           const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf, R* __restrict__ lphi0,
+           const uint8_t* __restrict__ rowflag, uint8_t* __restrict__ rowclear) {
   int64_t X;
   int xc[3];
   if (adj_cell(p.n, p.sy, p.sz, X, xc[0], xc[1], xc[2]))
-    adj_phi2_cell<D, N, NC, R>(p, X, xc, rflag, fbuf, fflag, cbuf, lphi0);
+    adj_phi2_cell<D, N, NC, R>(p, X, xc, rflag, fbuf, fflag, cbuf, lphi0, rowflag, rowclear);
 }
 
 // 5b + 1 of the step before.  The streaming/collision reverse of step n - 1
@@ -1057,7 +1076,7 @@ template <int D, int Q, int N, int NC, class R, bool TAPE>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_phi2_lbm(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
                const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf, R* __restrict__ lphi0,
-               const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
+               const uint8_t* __restrict__ rowflag, uint8_t* __restrict__ rowclear, const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
                const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
                const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
                R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
@@ -1065,7 +1084,7 @@ k_adj_phi2_lbm(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__
   int64_t P;
   int xc[3];
   if (adj_cell(p.n, p.sy, p.sz, P, xc[0], xc[1], xc[2])) {
-    adj_phi2_cell<D, N, NC, R>(p, P, xc, rflag, fbuf, fflag, cbuf, lphi0);
+    adj_phi2_cell<D, N, NC, R>(p, P, xc, rflag, fbuf, fflag, cbuf, lphi0, rowflag, rowclear);
     adj_lbm_cell<D, Q, N, NC, R, TAPE>(p, P, xc[0], xc[1], xc[2], fst, dr_t, u1, phi1, mu1, lf1, lu1, lmu1, lf0,
                                        t_phil, w, lmu0, gpart);
   }

@@ -73,6 +73,7 @@ struct gpf_ctx {
   hipEvent_t ev_free[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
   StateBuf lam[2];                 // adjoint state (phi, mu, U, post-streaming f)
   DevBuf t_phil, t_w, t_rbar, t_part, t_acc, t_slices, t_rflag, t_fflag, t_fbuf, t_cbuf;
+  DevBuf t_rowflag;                // per (y, z) row seed flags, two step parities
   int lam_cur = 0;                 // lam[lam_cur] holds the adjoint of the earliest state reached
   bool have_adjoint = false;
 };
@@ -557,6 +558,10 @@ struct Impl {
     return {dim3(nb), dim3(gpf::ADJ_BLOCK), static_cast<double*>(c->t_part.ptr), (int64_t)nb * gpf::NG,
             static_cast<uint8_t*>(c->t_rflag.ptr), static_cast<uint8_t*>(c->t_fflag.ptr)};
   }
+  // row seed flags of reverse step n (parity n mod 2)
+  static uint8_t* rowflags(gpf_ctx* c, int64_t n) {
+    return static_cast<uint8_t*>(c->t_rowflag.ptr) + (n & 1) * c->n[1] * c->n[2];
+  }
   static void adj_lbm(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, StateBuf& li, StateBuf& lo) {
     const AdjLaunch a = adj_launch(c);
     if (x1.dr)
@@ -573,28 +578,31 @@ struct Impl {
     const AdjLaunch a = adj_launch(c);
     hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R>), a.g, a.b, 0, c->stream, k, x0.phi, x1.phi,
                        x0.mu, x1.mu, x0.u, P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
-                       P(lo.mu), P(lo.u), P(c->t_rbar), a.rflag, (R)tshift(c, n), a.part + a.pstride);
+                       P(lo.mu), P(lo.u), P(c->t_rbar), a.rflag, rowflags(c, n), (R)tshift(c, n),
+                       a.part + a.pstride);
     hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), a.g, a.b, 0, c->stream, k, x0.phi, P(c->t_rbar), a.rflag,
                        P(c->t_fbuf), a.fflag, P(c->t_cbuf), a.part + 2 * a.pstride);
   }
-  // gather of step n into lo.phi alone (the last reverse step)
-  static void adj_phi2(gpf_ctx* c, const gpf::KP<R>& k, StateBuf& lo) {
+  // gather of step n into lo.phi alone
+  static void adj_phi2(gpf_ctx* c, const gpf::KP<R>& k, int64_t n, StateBuf& lo) {
     const AdjLaunch a = adj_launch(c);
     hipLaunchKernelGGL((gpf::k_adj_phi2<D, N, NC, R>), a.g, a.b, 0, c->stream, k, a.rflag, P(c->t_fbuf), a.fflag,
-                       P(c->t_cbuf), P(lo.phi));
+                       P(c->t_cbuf), P(lo.phi), rowflags(c, n), rowflags(c, n + 1));
   }
   // gather of step n into lo.phi, and the LBM reverse of step n - 1 (states
   // x0 = X^{n-1}, x1 = X^n) from lo (the adjoint of X^n) into li
-  static void adj_phi2_lbm(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, StateBuf& lo,
-                           StateBuf& li) {
+  static void adj_phi2_lbm(gpf_ctx* c, const gpf::KP<R>& k, int64_t n, const SP& x0, const SP& x1,
+                           StateBuf& lo, StateBuf& li) {
     const AdjLaunch a = adj_launch(c);
     if (x1.dr)
       hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, true>), a.g, a.b, 0, c->stream, k, a.rflag,
-                         P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), x0.f, x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
+                         P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), rowflags(c, n), rowflags(c, n + 1), x0.f,
+                         x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
                          P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), a.part);
     else
       hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, false>), a.g, a.b, 0, c->stream, k, a.rflag,
-                         P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), x0.f, x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
+                         P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), rowflags(c, n), rowflags(c, n + 1), x0.f,
+                         x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
                          P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), a.part);
   }
 
@@ -619,6 +627,7 @@ struct Impl {
       if (!rc) rc = dev_alloc(c, c->t_acc, gpf::NG * sizeof(double));
       if (!rc) rc = dev_alloc(c, c->t_slices, (size_t)gpf::GA * gpf::NG * sizeof(double));
       if (!rc) rc = dev_alloc(c, c->t_rflag, (size_t)c->cells);
+      if (!rc) rc = dev_alloc(c, c->t_rowflag, (size_t)2 * c->n[1] * c->n[2]);
       if (!rc) rc = dev_alloc(c, c->t_fflag, (size_t)D * c->cells);
       if (!rc) rc = dev_alloc(c, c->t_fbuf, (size_t)D * (2 + 4 * (D - 1)) * N * cs);
       if (!rc) rc = dev_alloc(c, c->t_cbuf, (size_t)(1 + 2 * D) * N * cs);
@@ -662,6 +671,8 @@ struct Impl {
     hipLaunchKernelGGL((gpf::k_fill<double>), dim3(1), dim3(gpf::NG), 0, c->stream,
                        static_cast<double*>(c->t_acc.ptr), (int64_t)gpf::NG, 0.0);
     // per-block running sums of the parameter derivatives over the sweep
+    hipLaunchKernelGGL((gpf::k_fill<uint8_t>), dim3(lin_blocks(2 * c->n[1] * c->n[2], 256)), dim3(256), 0,
+                       c->stream, static_cast<uint8_t*>(c->t_rowflag.ptr), 2 * c->n[1] * c->n[2], (uint8_t)0);
     const int64_t nparts = (int64_t)3 * adj_blocks(c->n);
     hipLaunchKernelGGL((gpf::k_fill<double>), dim3(lin_blocks(nparts * gpf::NG, 256)), dim3(256), 0, c->stream,
                        static_cast<double*>(c->t_part.ptr), nparts * gpf::NG, 0.0);
@@ -723,13 +734,13 @@ struct Impl {
           HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->ev_done[1 - b], 0));
         }
         if (fuse) {
-          adj_phi2_lbm(c, k, state(m - 1), state(m), *lo, *li);
+          adj_phi2_lbm(c, k, c->rec_start + m, state(m - 1), state(m), *lo, *li);
         } else {
-          adj_phi2(c, k, *lo);
+          adj_phi2(c, k, c->rec_start + m, *lo);
           adj_lbm(c, k, state(m - 1), state(m), *lo, *li);
         }
       } else {
-        adj_phi2(c, k, *lo);
+        adj_phi2(c, k, c->rec_start + m, *lo);
       }
       HIP_OR_FAIL(c, hipGetLastError());
       std::swap(li, lo);
@@ -1001,6 +1012,7 @@ void free_all(gpf_ctx* c) {
   dev_release(c, c->t_acc);
   dev_release(c, c->t_slices);
   dev_release(c, c->t_rflag);
+  dev_release(c, c->t_rowflag);
   dev_release(c, c->t_fflag);
   dev_release(c, c->t_fbuf);
   dev_release(c, c->t_cbuf);
