@@ -16,13 +16,18 @@ HIPCC_FLAGS = [
 
 
 def source_digest():
-    """sha256 over the kernel sources: identifies the kernels a profile was taken on"""
+    """sha256 over what defines the forward kernels (their sources and the
+    launch-shape constants): identifies the kernels a profile was taken on"""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(HERE, "csrc"))):
+    for name in ("gpf_device.hpp", "gpf_kernels.hpp"):
         with open(os.path.join(HERE, "csrc", name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
+    with open(os.path.join(HERE, "csrc", "gpf_runtime.hip")) as fh:
+        for line in fh:
+            if line.startswith("#define GPF_") or line.startswith("constexpr int kTileY"):
+                h.update(line.encode())
     return h.hexdigest()[:16]
 
 
