@@ -111,3 +111,17 @@ def test_moving_frame_needs_walls_on_the_pull_axis(gpf):
     cfg = workload("eutectic2d", periodic=[1, 1])
     rc, msg, h = _try_init(gpf, cfg, frame_every=10, frame_front=20)
     assert rc == -2 and "walls" in msg and not h.value
+
+
+def test_null_context_is_an_argument_error(gpf):
+    """Every entry point that takes a context answers GPF_ERR_ARG for NULL
+    (no device work, so this runs without a GPU)."""
+    L = gpf.lib()
+    names = (ctypes.c_char_p * 1)(b"D")
+    out = (ctypes.c_double * 1)()
+    seed = (ctypes.c_double * 4)()
+    assert L.gpf_adjoint(None, seed, 4, names, 1, out) == -1
+    assert L.gpf_adjoint_device(None, ctypes.c_void_p(1), 4, names, 1, out) == -1
+    assert L.gpf_adjoint_state(None, 0, seed, 4) == -1
+    assert L.gpf_record(None, 4) == -1
+    assert L.gpf_step(None, 1) == -1
