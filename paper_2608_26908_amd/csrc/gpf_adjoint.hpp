@@ -30,10 +30,13 @@ constexpr int ADJ_BLOCK = 256;
 // the rows [k ny / 8, (k + 1) ny / 8) of every plane and walks them plane by
 // plane.  A cell's neighbours in y and z are then, except at a slab edge,
 // read through the same L2, while all eight XCDs stream through the same
-// planes.  False for the padding slots at the end of an XCD's range.
+// planes.  False for the padding slots at the end of an XCD's range.  blk:
+// the work-group's index within a grid of the linear layout (a launch that
+// runs several such grids side by side passes blockIdx.x minus the offset of
+// its grid, a multiple of 8).
 __device__ __forceinline__ bool adj_cell(const int (&n)[3], int64_t sy, int64_t sz, int64_t& P, int& x,
-                                         int& y, int& z) {
-  const unsigned k = blockIdx.x % 8u, i = blockIdx.x / 8u;
+                                         int& y, int& z, unsigned blk = blockIdx.x) {
+  const unsigned k = blk % 8u, i = blk / 8u;
   const int y0 = (int)(((int64_t)k * n[1]) / 8);
   const unsigned h = (unsigned)((int)(((int64_t)(k + 1) * n[1]) / 8) - y0);
   const unsigned s = i * (unsigned)ADJ_BLOCK + threadIdx.x;
@@ -50,7 +53,8 @@ __device__ __forceinline__ bool adj_cell(const int (&n)[3], int64_t sy, int64_t 
 // order (shuffle tree within each wave, then the waves in turn), added to the
 // block's running sums over the reverse sweep: every block owns its slots, so
 // no atomics are needed and the result is deterministic.
-__device__ __forceinline__ void block_partials(double (&g)[NG], double* __restrict__ part) {
+__device__ __forceinline__ void block_partials(double (&g)[NG], double* __restrict__ part,
+                                               unsigned slot = blockIdx.x) {
   constexpr int NW = ADJ_BLOCK / 64;
   __shared__ double sh[NG][NW];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -66,7 +70,7 @@ __device__ __forceinline__ void block_partials(double (&g)[NG], double* __restri
     double s = sh[t][0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) s += sh[t][w];
-    part[(int64_t)blockIdx.x * NG + t] += s;
+    part[(int64_t)slot * NG + t] += s;
   }
 }
 
@@ -837,12 +841,17 @@ template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
           const uint8_t* __restrict__ rflag, R* __restrict__ fbuf, uint8_t* __restrict__ fflag,
-          R* __restrict__ cbuf, double* __restrict__ part) {
+          R* __restrict__ cbuf, double* __restrict__ part, int split) {
   constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
+  // split: D + 1 linear grids side by side, grid a < D for the faces along a,
+  // grid D for the cell terms (more waves in flight on small grids); else
+  // every thread does all of its cell's items
+  const unsigned nb = split ? gridDim.x / (unsigned)(D + 1) : gridDim.x;
+  const int item = split ? (int)(blockIdx.x / nb) : -1;
   int64_t L;
   int lc[3];
-  if (adj_cell(p.n, p.sy, p.sz, L, lc[0], lc[1], lc[2])) {
+  if (adj_cell(p.n, p.sy, p.sz, L, lc[0], lc[1], lc[2], blockIdx.x % nb)) {
     const int Lc[3] = {lc[0], lc[1], lc[2]};
     R rl[N];
 #pragma unroll
@@ -850,6 +859,7 @@ k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
     R dd_sum = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
+      if (item >= 0 && item != a) continue;
       int rcoord = 0;
       bool has = owner_coord(Lc[a] + 1, p.n[a], p.per[a], rcoord);  // false: wall face
       uint8_t flag = 0;
@@ -880,7 +890,7 @@ k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
       }
       fflag[(int64_t)a * p.cells + L] = flag;
     }
-    if (rflag[L]) {
+    if ((item < 0 || item == D) && rflag[L]) {
       R cbv[N];
 #pragma unroll
       for (int b = 0; b < N; ++b) cbv[b] = -p.eps * rl[b];
@@ -1071,7 +1081,9 @@ k_adj_phi2(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbu
 // 5b + 1 of the step before.  The streaming/collision reverse of step n - 1
 // reads the adjoint populations, mu and U of step n, which k_adj_lbm and
 // k_adj_muphi of step n wrote, but not lam phi^n: so it runs in the same
-// launch as the gather of step n (one kernel boundary less per step).
+// launch as the gather of step n (one kernel boundary less per step).  The
+// launch is two linear grids side by side: the first gathers, the second runs
+// the LBM reverse, so neither waits for the other.
 template <int D, int Q, int N, int NC, class R, bool TAPE>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_phi2_lbm(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__ fbuf,
@@ -1080,15 +1092,20 @@ k_adj_phi2_lbm(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__
                const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
                const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
                R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
-  double gpart[NG] = {0, 0, 0, 0, 0, 0};
+  const unsigned nb = gridDim.x / 2u;
   int64_t P;
   int xc[3];
-  if (adj_cell(p.n, p.sy, p.sz, P, xc[0], xc[1], xc[2])) {
-    adj_phi2_cell<D, N, NC, R>(p, P, xc, rflag, fbuf, fflag, cbuf, lphi0, rowflag, rowclear);
-    adj_lbm_cell<D, Q, N, NC, R, TAPE>(p, P, xc[0], xc[1], xc[2], fst, dr_t, u1, phi1, mu1, lf1, lu1, lmu1, lf0,
-                                       t_phil, w, lmu0, gpart);
+  if (blockIdx.x < nb) {
+    if (adj_cell(p.n, p.sy, p.sz, P, xc[0], xc[1], xc[2], blockIdx.x))
+      adj_phi2_cell<D, N, NC, R>(p, P, xc, rflag, fbuf, fflag, cbuf, lphi0, rowflag, rowclear);
+  } else {
+    const unsigned blk = blockIdx.x - nb;
+    double gpart[NG] = {0, 0, 0, 0, 0, 0};
+    if (adj_cell(p.n, p.sy, p.sz, P, xc[0], xc[1], xc[2], blk))
+      adj_lbm_cell<D, Q, N, NC, R, TAPE>(p, P, xc[0], xc[1], xc[2], fst, dr_t, u1, phi1, mu1, lf1, lu1, lmu1,
+                                         lf0, t_phil, w, lmu0, gpart);
+    block_partials(gpart, part, blk);
   }
-  block_partials(gpart, part);
 }
 
 // Sum the per-block running sums of the reverse sweep in a fixed order: each

@@ -553,6 +553,10 @@ struct Impl {
     int64_t pstride;
     uint8_t *rflag, *fflag;
   };
+  // Grids that do not fill the chip even at four waves per SIMD (256 CUs x
+  // 4 SIMDs x 4 x 64 cells): there every adjoint kernel is latency-bound, so
+  // the sweep trades work per thread for waves in flight and launches.
+  static bool small_grid(const gpf_ctx* c) { return c->cells <= (int64_t)256 * 4 * 4 * 64; }
   static AdjLaunch adj_launch(gpf_ctx* c) {
     const unsigned nb = adj_blocks(c->n);
     return {dim3(nb), dim3(gpf::ADJ_BLOCK), static_cast<double*>(c->t_part.ptr), (int64_t)nb * gpf::NG,
@@ -580,8 +584,10 @@ struct Impl {
                        x0.mu, x1.mu, x0.u, P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
                        P(lo.mu), P(lo.u), P(c->t_rbar), a.rflag, rowflags(c, n), (R)tshift(c, n),
                        a.part + a.pstride);
-    hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), a.g, a.b, 0, c->stream, k, x0.phi, P(c->t_rbar), a.rflag,
-                       P(c->t_fbuf), a.fflag, P(c->t_cbuf), a.part + 2 * a.pstride);
+    const int split = small_grid(c) ? 1 : 0;
+    hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), dim3(a.g.x * (split ? D + 1 : 1)), a.b, 0, c->stream, k,
+                       x0.phi, P(c->t_rbar), a.rflag, P(c->t_fbuf), a.fflag, P(c->t_cbuf), a.part + 2 * a.pstride,
+                       split);
   }
   // gather of step n into lo.phi alone
   static void adj_phi2(gpf_ctx* c, const gpf::KP<R>& k, int64_t n, StateBuf& lo) {
@@ -595,12 +601,14 @@ struct Impl {
                            StateBuf& lo, StateBuf& li) {
     const AdjLaunch a = adj_launch(c);
     if (x1.dr)
-      hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, true>), a.g, a.b, 0, c->stream, k, a.rflag,
+      hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, true>), dim3(2 * a.g.x), a.b, 0, c->stream, k,
+                         a.rflag,
                          P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), rowflags(c, n), rowflags(c, n + 1), x0.f,
                          x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
                          P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), a.part);
     else
-      hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, false>), a.g, a.b, 0, c->stream, k, a.rflag,
+      hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, false>), dim3(2 * a.g.x), a.b, 0, c->stream, k,
+                         a.rflag,
                          P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), rowflags(c, n), rowflags(c, n + 1), x0.f,
                          x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
                          P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), a.part);
@@ -623,7 +631,8 @@ struct Impl {
       if (!rc) rc = dev_alloc(c, c->t_phil, cs);
       if (!rc) rc = dev_alloc(c, c->t_w, NC * cs);
       if (!rc) rc = dev_alloc(c, c->t_rbar, N * cs);
-      if (!rc) rc = dev_alloc(c, c->t_part, (size_t)4 * nb * gpf::NG * sizeof(double));
+      // running sums: the LBM, mu / phi-local and (up to D + 1 grids) VJP reverses
+      if (!rc) rc = dev_alloc(c, c->t_part, (size_t)(D + 3) * nb * gpf::NG * sizeof(double));
       if (!rc) rc = dev_alloc(c, c->t_acc, gpf::NG * sizeof(double));
       if (!rc) rc = dev_alloc(c, c->t_slices, (size_t)gpf::GA * gpf::NG * sizeof(double));
       if (!rc) rc = dev_alloc(c, c->t_rflag, (size_t)c->cells);
@@ -673,7 +682,7 @@ struct Impl {
     // per-block running sums of the parameter derivatives over the sweep
     hipLaunchKernelGGL((gpf::k_fill<uint8_t>), dim3(lin_blocks(2 * c->n[1] * c->n[2], 256)), dim3(256), 0,
                        c->stream, static_cast<uint8_t*>(c->t_rowflag.ptr), 2 * c->n[1] * c->n[2], (uint8_t)0);
-    const int64_t nparts = (int64_t)3 * adj_blocks(c->n);
+    const int64_t nparts = (int64_t)(D + 3) * adj_blocks(c->n);
     hipLaunchKernelGGL((gpf::k_fill<double>), dim3(lin_blocks(nparts * gpf::NG, 256)), dim3(256), 0, c->stream,
                        static_cast<double*>(c->t_part.ptr), nparts * gpf::NG, 0.0);
     // slot j of segment sg in tape b holds X^{n0 + j} (slot 0 is the
@@ -701,11 +710,11 @@ struct Impl {
       if (m == total) return cur(c, c->cur);
       return slot(tape_of(sg), sg, j);
     };
-    // The gather and the next LBM reverse share a launch on grids that do not
-    // fill the chip even at four waves per SIMD (256 CUs x 4 SIMDs x 4 x 64
-    // cells): there the kernels are latency-bound and a boundary costs more
-    // than the fused kernel's registers (121, against 67 for the gather alone).
-    const bool fuse = c->cells <= (int64_t)256 * 4 * 4 * 64;
+    // On small grids the gather and the next LBM reverse share a launch, as
+    // two grids side by side (one kernel boundary less per step); on larger
+    // ones the combined kernel's registers (121, against 67 for the gather
+    // alone) cost more than the boundary.
+    const bool fuse = small_grid(c);
     for (int64_t j = 0; j < seg_len(nseg - 1) - 1; ++j) recompute_step(0, nseg - 1, j, c->stream);
     adj_lbm(c, k, state(total - 1), state(total), *li, *lo);
     int64_t nrec = 0, jr = 0;
