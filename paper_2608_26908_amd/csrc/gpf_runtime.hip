@@ -643,19 +643,48 @@ struct Impl {
       if (rc) return rc;
     }
     const int64_t nseg = (total + K - 1) / K;
-    const int ntape = nseg > 1 ? 2 : 1;
-    for (int b = 0; b < ntape; ++b) {
+    auto alloc_tape = [&](int b) -> int {
       while ((int64_t)c->tape[b].size() < K - 1) {
         StateBuf s;
-        rc = dev_alloc(c, s.phi, N * cs);
-        if (!rc) rc = dev_alloc(c, s.mu, NC * cs);
-        if (!rc) rc = dev_alloc(c, s.u, D * cs);
-        if (!rc) rc = dev_alloc(c, s.dr, cs);
-        if (rc) return rc;
+        int r = dev_alloc(c, s.phi, N * cs);
+        if (!r) r = dev_alloc(c, s.mu, NC * cs);
+        if (!r) r = dev_alloc(c, s.u, D * cs);
+        if (!r) r = dev_alloc(c, s.dr, cs);
+        if (r) {
+          dev_release(c, s.phi);
+          dev_release(c, s.mu);
+          dev_release(c, s.u);
+          return r;
+        }
         c->tape[b].push_back(s);
       }
-      for (int i = 0; i < 2 && K > 1; ++i)
-        if (!c->tape_f[b][i].ptr && (rc = dev_alloc(c, c->tape_f[b][i], Q * cs))) return rc;
+      for (int i = 0; i < 2 && K > 1; ++i) {
+        int r;
+        if (!c->tape_f[b][i].ptr && (r = dev_alloc(c, c->tape_f[b][i], Q * cs))) return r;
+      }
+      return GPF_OK;
+    };
+    // tape 0; with several segments, tape 1 for recomputing the previous
+    // segment on the second stream.  If tape 1 does not fit, each segment is
+    // recomputed into tape 0 on the library's stream before its reverse.
+    if ((rc = alloc_tape(0))) return rc;
+    int ntape = 1;
+    if (nseg > 1) {
+      if (alloc_tape(1) == GPF_OK) {
+        ntape = 2;
+      } else {
+        for (auto& st : c->tape[1]) {
+          dev_release(c, st.phi);
+          dev_release(c, st.mu);
+          dev_release(c, st.u);
+          dev_release(c, st.dr);
+        }
+        c->tape[1].clear();
+        dev_release(c, c->tape_f[1][0]);
+        dev_release(c, c->tape_f[1][1]);
+        (void)hipGetLastError();  // a failed hipMalloc leaves its error behind
+        c->err.clear();
+      }
     }
     if (ntape > 1 && !c->side) {
       HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
@@ -699,7 +728,7 @@ struct Impl {
     auto recompute_step = [&](int b, int64_t sg, int64_t j, hipStream_t st) {
       launch_step(c, k, slot(b, sg, j), slot(b, sg, j + 1), (R)tshift(c, c->rec_start + sg * K + j), st, nullptr);
     };
-    auto tape_of = [&](int64_t sg) { return (int)((nseg - 1 - sg) & 1); };
+    auto tape_of = [&](int64_t sg) { return ntape == 2 ? (int)((nseg - 1 - sg) & 1) : 0; };
     // X^{rec_start + m}, m in [0, total]: the checkpoints every K steps, the
     // current state at m = total (neither holds rho - rho0, so the LBM reverse
     // of the step that ends there reads its populations), else slot m mod K
@@ -726,9 +755,9 @@ struct Impl {
         // other tape once everything that read that tape (already queued) is
         // done; its steps are queued alternately with the reverse steps, so
         // neither stream waits for the host to queue the other's work
-        nrec = (sg > 0) ? K - 1 : 0;
+        nrec = (sg > 0 && ntape == 2) ? K - 1 : 0;
         jr = 0;
-        if (sg > 0) {
+        if (sg > 0 && ntape == 2) {
           HIP_OR_FAIL(c, hipEventRecord(c->ev_free[1 - b], c->stream));
           HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->ev_free[1 - b], 0));
         }
@@ -736,11 +765,15 @@ struct Impl {
       adj_muphi_vjp(c, k, state(m), state(m + 1), c->rec_start + m, *li, *lo);
       if (jr < nrec) recompute_step(1 - b, sg - 1, jr++, c->side);
       if (m > 0) {
-        if (j == 0) {
+        if (j == 0 && ntape == 2) {
           // step m - 1 lies in the previous segment: its tape must be complete
           while (jr < nrec) recompute_step(1 - b, sg - 1, jr++, c->side);
           HIP_OR_FAIL(c, hipEventRecord(c->ev_done[1 - b], c->side));
           HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->ev_done[1 - b], 0));
+        } else if (j == 0) {
+          // one tape: the previous segment replaces this one, whose last
+          // reader (the reverse of step m) is already queued
+          for (int64_t jj = 0; jj < K - 1; ++jj) recompute_step(0, sg - 1, jj, c->stream);
         }
         if (fuse) {
           adj_phi2_lbm(c, k, c->rec_start + m, state(m - 1), state(m), *lo, *li);

@@ -163,9 +163,11 @@ class Sim:
     cfg: a workload dict (paper_2608_26908_amd.workloads); precision 'fp64'
     or 'fp32' (default: cfg['precision']).  Device memory comes from torch's
     caching allocator unless torch_alloc=False (then hipMalloc); kernels run
-    on torch's current stream."""
+    on torch's current stream.  memory_limit (bytes, torch allocator only):
+    allocations beyond it fail as if the device were full."""
 
-    def __init__(self, cfg, precision=None, seed=None, torch_alloc=True, health_every=None):
+    def __init__(self, cfg, precision=None, seed=None, torch_alloc=True, health_every=None,
+                 memory_limit=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the library runs only on the device")
@@ -183,10 +185,20 @@ class Sim:
         if torch_alloc:
             torch.cuda.init()
 
+            held = self._held = {}
+
             def _alloc(nbytes, user):
-                return torch.cuda.caching_allocator_alloc(int(nbytes))
+                if memory_limit is not None and self.device_bytes + int(nbytes) > memory_limit:
+                    return None
+                try:
+                    ptr = torch.cuda.caching_allocator_alloc(int(nbytes))
+                except torch.cuda.OutOfMemoryError:
+                    return None
+                held[ptr] = int(nbytes)
+                return ptr
 
             def _free(ptr, user):
+                held.pop(ptr, None)
                 torch.cuda.caching_allocator_delete(ptr)
             self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
             self._params.dev_alloc, self._params.dev_free = self._cb
@@ -199,6 +211,11 @@ class Sim:
         self._h = h
         _LIVE.add(self)
         self._check(L.gpf_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    @property
+    def device_bytes(self):
+        """device memory the context holds through torch's allocator"""
+        return sum(getattr(self, "_held", {}).values())
 
     # -- plumbing ----------------------------------------------------------
     def _check(self, rc):

@@ -215,3 +215,34 @@ def test_adjoint_large_grid_against_central_differences():
         fd = (loss(name, v * (1 + h)) - loss(name, v * (1 - h))) / (2 * h * v)
         assert gv == pytest.approx(fd, rel=1e-5), (name, gv, fd)
     g.close()
+
+
+def test_one_tape_when_the_second_does_not_fit():
+    """With several checkpoint segments the sweep recomputes the previous
+    segment into a second tape on a second stream; when that tape does not fit
+    in device memory it recomputes every segment into the first tape on the
+    library's stream instead.  Same kernels on the same values: the gradients
+    and the adjoint state are bitwise those of the two-tape sweep."""
+    from paper_2608_26908_amd.gpf import Sim
+    cfg = scaled("eutectic3d", [24, 20, 16], lam_height=6.0, y0=6.0)
+    steps, K = 14, 4
+    names = ["D", "D1", "tau_pf"]
+    a = Sim(cfg, precision="fp64")
+    a.record(K)
+    a.step(steps)
+    phi = a.read("phi")
+    seed = np.cos(np.arange(phi.size)).reshape(phi.shape)
+    ga = a.adjoint(seed, names)
+    la = a.adjoint_state("mu")
+    two = a.device_bytes
+    cells = 24 * 20 * 16
+    tape = ((K - 1) * (3 + 2 + 3 + 1) + 2 * 19) * cells * 8
+    a.close()
+    b = Sim(cfg, precision="fp64", memory_limit=two - tape // 2)
+    b.record(K)
+    b.step(steps)
+    gb = b.adjoint(seed, names)
+    assert b.device_bytes <= two - tape + 4096
+    assert np.array_equal(ga, gb)
+    assert np.array_equal(la, b.adjoint_state("mu"))
+    b.close()
