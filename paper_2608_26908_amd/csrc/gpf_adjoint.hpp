@@ -841,7 +841,7 @@ template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
           const uint8_t* __restrict__ rflag, R* __restrict__ fbuf, uint8_t* __restrict__ fflag,
-          R* __restrict__ cbuf, double* __restrict__ part, int split) {
+          R* __restrict__ cbuf, double* __restrict__ part, const uint8_t* __restrict__ rowflag, int split) {
   constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
   // split: D + 1 linear grids side by side, grid a < D for the faces along a,
@@ -851,7 +851,20 @@ k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
   const int item = split ? (int)(blockIdx.x / nb) : -1;
   int64_t L;
   int lc[3];
-  if (adj_cell(p.n, p.sy, p.sz, L, lc[0], lc[1], lc[2], blockIdx.x % nb)) {
+  // the cell's faces and its cell term carry a seed only if its row or the
+  // rows of its +y and +z neighbours hold one (row flags of k_adj_muphi)
+  auto seeded_rows = [&](const int (&c3)[3]) {
+    const int yn = nb_field(c3[1], 1, p.n[1], p.per[1]);
+    bool r = rowflag[(int64_t)c3[2] * p.n[1] + c3[1]] | rowflag[(int64_t)c3[2] * p.n[1] + yn];
+    if (D == 3) r = r | rowflag[(int64_t)nb_field(c3[2], 1, p.n[2], p.per[2]) * p.n[1] + c3[1]];
+    return r;
+  };
+  const bool valid = adj_cell(p.n, p.sy, p.sz, L, lc[0], lc[1], lc[2], blockIdx.x % nb);
+  if (valid && !seeded_rows(lc)) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      if (item < 0 || item == a) fflag[(int64_t)a * p.cells + L] = 0;
+  } else if (valid) {
     const int Lc[3] = {lc[0], lc[1], lc[2]};
     R rl[N];
 #pragma unroll

@@ -587,7 +587,7 @@ struct Impl {
     const int split = small_grid(c) ? 1 : 0;
     hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), dim3(a.g.x * (split ? D + 1 : 1)), a.b, 0, c->stream, k,
                        x0.phi, P(c->t_rbar), a.rflag, P(c->t_fbuf), a.fflag, P(c->t_cbuf), a.part + 2 * a.pstride,
-                       split);
+                       rowflags(c, n), split);
   }
   // gather of step n into lo.phi alone
   static void adj_phi2(gpf_ctx* c, const gpf::KP<R>& k, int64_t n, StateBuf& lo) {
