@@ -155,8 +155,9 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
             in = false;
         }
       }
-      ob[k] = in ? lf1[k * p.cells + (int64_t)dst[2] * p.sz + (int64_t)dst[1] * p.sy + dst[0]]
-                 : lf1[L::opp(k) * p.cells + P];
+      // every adjoint population is read once per reverse step: a streaming load
+      ob[k] = __builtin_nontemporal_load(in ? &lf1[k * p.cells + (int64_t)dst[2] * p.sz + (int64_t)dst[1] * p.sy + dst[0]]
+                                            : &lf1[L::opp(k) * p.cells + P]);
     }
     const R phil = phi1[(N - 1) * p.cells + P];
     R mu[NC];
@@ -285,7 +286,7 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
 #pragma unroll
       for (int a = 0; a < D; ++a)
         if (L::c(k, a) != 0) v += mb[a] * R(L::c(k, a));
-      lf0[k * p.cells + P] = v;
+      __builtin_nontemporal_store(v, &lf0[k * p.cells + P]);
     }
     t_phil[P] = philb;
     // lam mu' in full, its direct pass to lam mu^n (mu' = mu + ...) and
