@@ -200,17 +200,17 @@ __device__ __forceinline__ void pf_rhs(const KP<R>& p, const R (&v)[N][3][3][3],
 }
 
 // phi^{n+1} of a cell from its neighbourhood v and mu^n: unchanged when one
-// phase is active, else the projection of phi + dt/(tau eps) R over the
-// active phases onto the simplex.  theta returns the projection's shift.
+// phase is active (bulk, returned true), else the projection of
+// phi + dt/(tau eps) R over the active phases onto the simplex.
 template <int D, int N, int NC, class R>
-__device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N][3][3][3],
+__device__ __forceinline__ bool phi_from_stencil(const KP<R>& p, const R (&v)[N][3][3][3],
                                                  const R* __restrict__ mu, int x, int y, int z,
                                                  R tshift, R (&res)[N]) {
   const unsigned active = active_of<D, N, R>(v);
   if (__builtin_popcount(active) <= 1) {  // bulk: phi unchanged
 #pragma unroll
     for (int b = 0; b < N; ++b) res[b] = v[b][1][1][1];
-    return;
+    return true;
   }
   R Rv[N], vv[N];
   pf_rhs<D, N, NC, R>(p, v, mu, x, y, z, tshift, Rv);
@@ -218,6 +218,7 @@ __device__ __forceinline__ void phi_from_stencil(const KP<R>& p, const R (&v)[N]
   for (int b = 0; b < N; ++b) vv[b] = v[b][1][1][1] + p.rate * Rv[b];
   R theta;
   project_masked<N, R>(active, vv, res, theta);
+  return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -453,7 +454,8 @@ __device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty
 template <int D, int N, int NC, class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
 k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
-        R tshift, int tiles_x, int tiles_y, int zc) {
+        const uint8_t* __restrict__ bulk_in, uint8_t* __restrict__ bulk_out, R tshift, int tiles_x, int tiles_y,
+        int zc) {
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
   constexpr int NT = TX * TY, PER = (HC + NT - 1) / NT;  // halo-tile cells per thread
   constexpr int NS = (D == 3) ? 4 : 1;
@@ -464,6 +466,13 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
   const int x = T.x0 + lx, y = T.y0 + ly;
   const bool own = x < p.n[0] && y < p.n[1];
   const int c0 = (ly + 1) * HX + (lx + 1);
+  // Bulk history (both null when phi_out is not the buffer that held phi^{n-1}):
+  // bulk_in[block] says every cell of this block's tile and planes was bulk in
+  // the step that produced phi^n from phi^{n-1}, so phi_out, which still holds
+  // phi^{n-1}, already holds phi^n there, and a cell that is bulk again (phi^{n+1}
+  // = phi^n) need not be stored.  bulk_out[block] records the same for this step.
+  const bool was_bulk = bulk_in && bulk_in[blockIdx.x];
+  int all_bulk = 1;
 
   // in-plane offsets of this thread's halo-tile cells (fixed along z)
   int64_t hoff[PER];
@@ -507,10 +516,16 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
           for (int q = 0; q < N; ++q) v[q][dz + 1][dy + 1][dx + 1] = ring[sl[dz + 1]][q][c0 + dy * HX + dx];
         }
     R res[N];
-    phi_from_stencil<D, N, NC, R>(p, v, mu, xq, yq, z, tshift, res);
+    const bool bulk = phi_from_stencil<D, N, NC, R>(p, v, mu, xq, yq, z, tshift, res);
+    all_bulk &= bulk ? 1 : 0;
+    if (was_bulk && bulk) return;
     const int64_t P = (int64_t)z * p.sz + (int64_t)yq * p.sy + xq;
 #pragma unroll
     for (int q = 0; q < N; ++q) __builtin_nontemporal_store(res[q], &phi_out[q * p.cells + P]);
+  };
+  auto record_bulk = [&]() {
+    const int b = __syncthreads_and(all_bulk);
+    if (bulk_out && tid == 0) bulk_out[blockIdx.x] = (uint8_t)b;
   };
 
   if (D == 2) {
@@ -518,6 +533,7 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
     store(0);
     __syncthreads();
     update(0, 0, 0, 0);
+    record_bulk();
     return;
   }
   // ring slot of plane zz: (zz - z0 + 1) mod 4
@@ -540,6 +556,7 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
       __syncthreads();
     }
   }
+  record_bulk();
 }
 
 // ---------------------------------------------------------------------------

@@ -58,6 +58,10 @@ struct gpf_ctx {
   DevBuf redout;    // final reduction values
   DevBuf badstep;   // health: smallest failing step
   DevBuf frontbuf;  // moving frame: front position found on the device
+  // per k_phi_z block: the step that produced state buffer i left phi
+  // unchanged on the block's cells (valid while bulk_ok[i])
+  DevBuf bulkf[2];
+  bool bulk_ok[2] = {false, false};
   int64_t frame_off = 0;  // moving frame: cells shifted so far along the pull axis
   const Ops* ops = nullptr;
   std::string err;
@@ -243,6 +247,12 @@ inline unsigned adj_blocks(const int64_t (&n)[3]) {
 #define GPF_ZCHUNK_MU 4
 #endif
 constexpr int kTileY = GPF_TILE_Y, kZChunkPhi = GPF_ZCHUNK_PHI, kZChunkMu = GPF_ZCHUNK_MU;
+// blocks of one k_phi_z launch (64 x kTileY tiles, kZChunkPhi planes each in 3D)
+inline int64_t phi_blocks(const gpf_ctx* c) {
+  const int64_t tx = (c->n[0] + 63) / 64, ty = (c->n[1] + kTileY - 1) / kTileY;
+  const int64_t tz = (c->dim == 3) ? (c->n[2] + kZChunkPhi - 1) / kZChunkPhi : 1;
+  return tx * ty * tz;
+}
 
 template <int D, int Q, int N, int NC, class R>
 struct Impl {
@@ -267,8 +277,11 @@ struct Impl {
     return SP{P(c->phi[s]), P(c->mu[s]), P(c->u[s]), P(c->f[s]), nullptr};
   }
 
+  // bulk_in / bulk_out: k_phi_z's bulk history, only for a step from one
+  // state buffer into the other (null elsewhere)
   static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& in, const SP& out, R ts,
-                          hipStream_t st, hipEvent_t* ev) {
+                          hipStream_t st, hipEvent_t* ev, const uint8_t* bulk_in = nullptr,
+                          uint8_t* bulk_out = nullptr) {
     constexpr int TX = 64, TY = kTileY;
     const int tiles_x = (int)((c->n[0] + TX - 1) / TX), tiles_y = (int)((c->n[1] + TY - 1) / TY);
     auto grid = [&](int zc) {
@@ -278,7 +291,7 @@ struct Impl {
     const dim3 block(TX * TY);
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid(kZChunkPhi), block, 0, st, k, in.phi,
-                       in.mu, out.phi, ts, tiles_x, tiles_y, kZChunkPhi);
+                       in.mu, out.phi, bulk_in, bulk_out, ts, tiles_x, tiles_y, kZChunkPhi);
     if (ev) (void)hipEventRecord(ev[1], st);
     if (k.shrink)
       hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, true>), grid(kZChunkMu), block, 0, st, k,
@@ -330,6 +343,7 @@ struct Impl {
     HIP_OR_FAIL(c, hipGetLastError());
     c->cur = t;
     c->frame_off += d;
+    c->bulk_ok[0] = c->bulk_ok[1] = false;
     return GPF_OK;
   }
 
@@ -344,8 +358,11 @@ struct Impl {
     for (int64_t it = 0; it < nsteps; ++it) {
       const int s = c->cur, t = 1 - c->cur;
       const R ts = (R)tshift(c, c->step);
-      launch_step(c, k, cur(c, s), cur(c, t), ts, c->stream, kernel_ms ? ev : nullptr);
+      launch_step(c, k, cur(c, s), cur(c, t), ts, c->stream, kernel_ms ? ev : nullptr,
+                  c->bulk_ok[s] ? static_cast<const uint8_t*>(c->bulkf[s].ptr) : nullptr,
+                  static_cast<uint8_t*>(c->bulkf[t].ptr));
       HIP_OR_FAIL(c, hipGetLastError());
+      c->bulk_ok[t] = true;
       if (kernel_ms) {
         HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
         float a = 0.f, b = 0.f;
@@ -1020,6 +1037,8 @@ void free_all(gpf_ctx* c) {
   dev_release(c, c->redout);
   dev_release(c, c->badstep);
   dev_release(c, c->frontbuf);
+  dev_release(c, c->bulkf[0]);
+  dev_release(c, c->bulkf[1]);
   auto rel = [&](StateBuf& s) {
     dev_release(c, s.phi);
     dev_release(c, s.mu);
@@ -1123,6 +1142,7 @@ int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_co
   if (!rc) rc = dev_alloc(c, c->redout, 4 * sizeof(double));
   if (!rc) rc = dev_alloc(c, c->badstep, sizeof(unsigned long long));
   if (!rc) rc = dev_alloc(c, c->frontbuf, sizeof(int));
+  for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(c, c->bulkf[i], (size_t)phi_blocks(c));
   if (!rc) {
     hipError_t e = hipMemsetAsync(c->badstep.ptr, 0xff, sizeof(unsigned long long), c->stream);
     if (e != hipSuccess) rc = fail(c, GPF_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
@@ -1201,6 +1221,7 @@ int gpf_write(gpf_ctx* c, int32_t field, const double* src, size_t count) {
   if (!c || !src) return GPF_ERR_ARG;
   int rc = write_host(c, field, src, count);
   if (rc) return rc;
+  c->bulk_ok[0] = c->bulk_ok[1] = false;  // the buffers no longer hold consecutive states
   // a written state starts a fresh health record
   HIP_OR_FAIL(c, hipMemsetAsync(c->badstep.ptr, 0xff, sizeof(unsigned long long), c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));

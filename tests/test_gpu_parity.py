@@ -168,6 +168,31 @@ def test_checkpoint_resume_is_bitwise(name, precision):
         assert np.array_equal(a.read(k), b.read(k)), k
 
 
+def test_written_state_is_stepped_in_full():
+    """k_phi_z leaves a block's bulk cells unstored when the step before left
+    them unchanged too (the output buffer still holds phi^n there); a written
+    state voids that history.  A slab turned from melt into solid (bulk before
+    and after, so only the voided history makes its cells be stored) steps
+    bitwise as in a context that starts from the written state."""
+    cfg = scaled("dendrite3d", [64, 64, 40])
+    a = _sim(cfg, "fp64")
+    a.step(6)
+    st, n, off = a.checkpoint()
+    phi = st["phi"].copy()
+    phi[0, :20, :8, :] = 1.0   # solid: z < 20, y < 8, every x (whole k_phi_z tiles)
+    phi[1, :20, :8, :] = 0.0
+    st = dict(st, phi=phi)
+    a.restore((st, n, off))
+    b = _sim(cfg, "fp64")
+    b.restore((st, n, off))
+    a.step(3)
+    b.step(3)
+    for k in STATE:
+        assert np.array_equal(a.read(k), b.read(k)), k
+    # the slab's inside (away from its faces) stayed solid
+    assert np.array_equal(a.read("phi")[0, :16, :4, :], phi[0, :16, :4, :])
+
+
 def test_full_f_write_matches_oracle_state(oracle):
     """writing the post-streaming f (full populations) reproduces it on read"""
     cfg = busy_config("binary2d", [33, 17], lid_u=0.02, periodic=[0, 0])
