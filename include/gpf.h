@@ -200,7 +200,10 @@ int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
  * steps (device memory: (N + nc + dim + Q) * cells values per checkpoint;
  * gpf_adjoint adds a tape of checkpoint_every - 1 states of
  * (N + nc + dim + 1) * cells values, two population buffers and the adjoint
- * state).  Checkpoint m belongs to step (start + m checkpoint_every): a state
+ * state; with more than one segment a second tape, into which the previous
+ * segment is recomputed on a second stream during the reverse of the current
+ * one, when it fits: if its allocation fails the sweep runs with one tape,
+ * bitwise the same results).  Checkpoint m belongs to step (start + m checkpoint_every): a state
  * restored to an earlier step and stepped again overwrites the later ones;
  * gpf_step fails with GPF_ERR_STATE at a checkpoint step before the start of
  * the recording or past the next checkpoint in sequence.
