@@ -101,6 +101,10 @@ def test_adjoint_leaves_forward_state_and_is_deterministic():
     import torch
     c = g.adjoint(torch.tensor(seed, dtype=torch.float64, device="cuda"), ["delta", "tau_pf", "D", "gbeta"])
     assert np.array_equal(a, c)
+    # a device seed of the wrong size is refused before any work
+    from paper_2608_26908_amd.gpf import GPFError
+    with pytest.raises(GPFError, match="GPF_ERR_ARG"):
+        g.adjoint(torch.zeros(5, dtype=torch.float64, device="cuda"), ["delta"])
     assert np.array_equal(g.read("phi"), phi)
     assert g.step_index == 12
 
