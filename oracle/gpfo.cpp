@@ -1101,6 +1101,24 @@ void gpfo_guo(int32_t Q, double tau, const double* u, const double* F, double* S
 }
 double gpfo_normal(uint64_t seed, uint64_t j) { return normal_j(seed, j); }
 
+int gpfo_grand_potential(const gpfo_params* prm, int32_t a, const double* mu, double T, double h,
+                         double* psi_out, double* dpsi_dmu, double* dpsi_dT, double* conc) {
+  if (!prm || a < 0 || a >= prm->N || prm->nc < 1 || prm->nc > 2 || !(h > 0)) return -1;
+  const Par<double> pd = lift<double>(*prm);
+  const Par<cplx> pc = lift<cplx>(*prm);
+  *psi_out = psi(pd, a, mu, T);
+  for (int i = 0; i < prm->nc; ++i) {
+    cplx m[2];
+    for (int j = 0; j < prm->nc; ++j) m[j] = cplx(mu[j], j == i ? h : 0.0);
+    dpsi_dmu[i] = psi(pc, a, m, cplx(T)).imag() / h;
+  }
+  cplx m[2];
+  for (int j = 0; j < prm->nc; ++j) m[j] = cplx(mu[j]);
+  *dpsi_dT = psi(pc, a, m, cplx(T, h)).imag() / h;
+  comp_C(pd, a, mu, conc);
+  return 0;
+}
+
 int gpfo_loss_grad_cs(const gpfo_sim* s, int64_t nsteps, const double* target, int32_t which,
                       double h, double* loss_out, double* grad_out) {
   Par<cplx> p = lift<cplx>(s->prm);

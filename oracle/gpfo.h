@@ -115,6 +115,12 @@ void gpfo_interp_h(int32_t N, const double* phi, double* h, double* dh /* N*N, d
 void gpfo_feq(int32_t Q, double rho, const double* u, double* feq);
 void gpfo_guo(int32_t Q, double tau, const double* u, const double* F, double* S);
 double gpfo_normal(uint64_t seed, uint64_t j);
+/* Grand potential psi^a(mu, T) of phase a under the parameters p, with its
+ * complex-step derivatives d psi^a / d mu_i (nc values) and d psi^a / d T
+ * (step h), and the composition C^a_i(mu, T) (nc values): the pointwise
+ * pieces of the grand-potential relation -d psi^a / d mu = C^a. */
+int gpfo_grand_potential(const gpfo_params* p, int32_t a, const double* mu, double T, double h,
+                         double* psi_out, double* dpsi_dmu, double* dpsi_dT, double* conc);
 
 /* Complex-step derivative of L = 1/2 sum (phi_T - target)^2 after nsteps
  * steps from the state of `s` (left untouched), with respect to parameter

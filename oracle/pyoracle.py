@@ -98,6 +98,8 @@ def lib():
         L.gpfo_guo.argtypes = [i32, d, dp, dp, dp]
         L.gpfo_normal.restype = d
         L.gpfo_normal.argtypes = [u64, u64]
+        L.gpfo_grand_potential.restype = i32
+        L.gpfo_grand_potential.argtypes = [P(_Params), i32, dp, d, d, dp, dp, dp, dp]
         L.gpfo_loss_grad_cs.argtypes = [vp, i64, dp, i32, d, dp, dp]
         L.gpfo_tangent_cs.argtypes = [vp, i64, i32, dp, d, i32, dp]
         _lib = L
@@ -305,3 +307,18 @@ def guo(dim, tau, u, F, Q=None):
 
 def normal(seed, j):
     return lib().gpfo_normal(seed, j)
+
+
+def grand_potential(cfg, a, mu, T, h=1e-30):
+    """(psi^a, d psi^a/d mu by complex step, d psi^a/d T by complex step,
+    C^a(mu)) at chemical potential mu (nc values) and temperature T."""
+    prm = make_params(cfg)
+    nc = cfg["nc"]
+    mu = np.ascontiguousarray(mu, dtype=float)
+    psi, dT = ctypes.c_double(), ctypes.c_double()
+    dmu, conc = np.zeros(nc), np.zeros(nc)
+    rc = lib().gpfo_grand_potential(ctypes.byref(prm), a, _dp(mu), float(T), h, ctypes.byref(psi),
+                                    _dp(dmu), ctypes.byref(dT), _dp(conc))
+    if rc != 0:
+        raise ValueError("gpfo_grand_potential: invalid arguments")
+    return psi.value, dmu, dT.value, conc
