@@ -84,7 +84,14 @@ typedef enum {
   GPF_FPOST = 8
 } gpf_field;
 
-typedef enum { GPF_SUM_SOLUTE = 0, GPF_SUM_MASS = 1 } gpf_reduction;
+/* FP64 totals of gpf_reduce:
+ *   GPF_SUM_SOLUTE  nc values  sum over cells of the mixture composition sum_a h_a C^a_i(mu), the
+ *                              quantity Eq. (conc) conserves (flux form, zero-flux walls)
+ *   GPF_SUM_MASS    1 value    sum over cells of rho = sum_k f_k, Eq. (rhovel)
+ *   GPF_LOSS        1 value    L = 1/2 sum over cells and phases of (phi_a - phi^target_a)^2 against
+ *                              the target of gpf_set_target (the paper has no loss: the scalar whose
+ *                              parameter gradients gpf_adjoint computes) */
+typedef enum { GPF_SUM_SOLUTE = 0, GPF_SUM_MASS = 1, GPF_LOSS = 2 } gpf_reduction;
 
 typedef struct {
   int32_t dim;            /* 2 or 3 */
@@ -154,7 +161,9 @@ int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_co
              const gpf_params* params, uint64_t seed);
 
 /* Launch subsequent work on this HIP stream (a hipStream_t, e.g. torch's
- * current stream); NULL selects the null stream.  The stream is not owned. */
+ * current stream); NULL selects the null stream.  The stream is not owned.
+ * Not an operation of the paper: it places the passes of Algorithm phfLBM
+ * (App. A) on the caller's stream.  Errors: GPF_ERR_ARG (NULL ctx). */
 int gpf_set_stream(gpf_ctx* ctx, void* hip_stream);
 
 /* Advance n >= 0 coupled steps (Algorithm phfLBM, one pass per step).
@@ -163,34 +172,61 @@ int gpf_set_stream(gpf_ctx* ctx, void* hip_stream);
  * failing step in the message) when it failed. */
 int gpf_step(gpf_ctx* ctx, int64_t n);
 
-/* Like gpf_step, and records HIP events around every kernel launch on the
- * context's stream; kernel_ms[j] receives the summed milliseconds of kernel
+/* Like gpf_step (Algorithm phfLBM, App. A), and records HIP events around
+ * every kernel launch on the context's stream; kernel_ms[j] receives the summed milliseconds of kernel
  * j of the step (j = 0: phase field, 1: chemical potential + LBM), count
  * up to n_kernels.  Synchronises.  For measurement only. */
 int gpf_step_timed(gpf_ctx* ctx, int64_t n, double* kernel_ms, int32_t n_kernels);
 
 /* Copy a field to caller-owned host memory as FP64 (adds w_k rho0 back to f
- * in every precision).  count must equal components * cells.  Synchronises. */
+ * in every precision): the output step of Algorithm phfLBM (App. A), which
+ * writes rho, phi, U and C, plus mu, f, T and the active-set flags.  count
+ * must equal components * cells.  Synchronises.  Errors: GPF_ERR_ARG (NULL,
+ * unknown field, wrong count), GPF_ERR_DEVICE. */
 int gpf_read(gpf_ctx* ctx, int32_t field, double* host_dst, size_t count);
 
 /* Copy a field to caller-owned device memory in the context's precision
- * (double or float; f as the full f).  bytes must equal components * cells *
- * element size.  Asynchronous on the context's stream. */
+ * (double or float; f as the full f): the output step of Algorithm phfLBM
+ * without leaving the device.  GPF_PHI, GPF_MU, GPF_U, GPF_F only.  bytes
+ * must equal components * cells * element size.  Asynchronous on the
+ * context's stream.  Errors: GPF_ERR_ARG, GPF_ERR_DEVICE. */
 int gpf_read_device(gpf_ctx* ctx, int32_t field, void* dev_dst, size_t bytes);
 
 /* Overwrite a state field from FP64 host memory (GPF_PHI, GPF_MU, GPF_F as
- * the post-streaming f^n, GPF_U as the velocity of the previous step).
- * Synchronises.  Used by tests to inject states. */
+ * the post-streaming f^n, GPF_U as the velocity of the previous step,
+ * GPF_FPOST as the stored post-collision populations): the state that the
+ * initialisation step of Algorithm phfLBM (App. A) sets, given by the caller
+ * (tests inject states; resuming writes a checkpoint back).  Synchronises.
+ * Errors: GPF_ERR_ARG (NULL, field not writable, wrong count), GPF_ERR_DEVICE. */
 int gpf_write(gpf_ctx* ctx, int32_t field, const double* host_src, size_t count);
 
-/* FP64 totals in a fixed summation order (deterministic): GPF_SUM_SOLUTE
- * writes nc values sum_cells sum_a h_a C^a_i(mu); GPF_SUM_MASS one value
- * sum_cells sum_k f_k.  Synchronises. */
+/* FP64 totals in a fixed summation order (deterministic), see gpf_reduction:
+ * the solute that Eq. (conc) conserves, the mass of Eq. (rhovel), or the
+ * loss against the target.  out receives nc values (GPF_SUM_SOLUTE) or one.
+ * Synchronises.  Errors: GPF_ERR_ARG (NULL, unknown reduction),
+ * GPF_ERR_STATE (GPF_LOSS without a target), GPF_ERR_DEVICE. */
 int gpf_reduce(gpf_ctx* ctx, int32_t which, double* out);
 
-/* Change one scalar parameter between steps: "delta" (all anisotropic
- * pairs), "tau_pf", "D" / "D1" (liquid diffusivity of solute 0 / 1),
- * "gbeta" / "gbeta1".  Re-validated like gpf_init. */
+/* Target phi^target of the loss GPF_LOSS: caller-owned device memory, FP64,
+ * N * cells values in the layout of GPF_PHI.  The context keeps the pointer
+ * (not the memory): it must stay valid until replaced or cleared (NULL, with
+ * count 0).  The paper has no loss; the target is the final microstructure
+ * whose parameters the adjoint inverts.  Errors: GPF_ERR_ARG (wrong count). */
+int gpf_set_target(gpf_ctx* ctx, const void* dev_target, size_t count);
+
+/* dL/dphi = phi - phi^target of the loss GPF_LOSS at the current state, FP64,
+ * into caller-owned device memory of N * cells values (the seed that
+ * gpf_adjoint_device takes).  Asynchronous on the context's stream.
+ * Errors: GPF_ERR_ARG (NULL, wrong count), GPF_ERR_STATE (no target). */
+int gpf_loss_seed_device(gpf_ctx* ctx, void* dev_seed, size_t count);
+
+/* Change one scalar parameter between steps: "delta" (anisotropy strength
+ * of the gradient energy a(phi, grad phi) of Eq. (PhfGrand), all anisotropic
+ * pairs), "tau_pf" (relaxation tau of Eq. (PhfGrand)), "D" / "D1" (liquid
+ * diffusivity of solute 0 / 1 in the mobility M of Eq. (conc)), "gbeta" /
+ * "gbeta1" (products g beta_i of Eq. (buoyancy)): the parameters the adjoint
+ * differentiates.  Re-validated like gpf_init.  Errors: GPF_ERR_ARG (unknown
+ * name), GPF_ERR_PARAM (invalid value; the context is then unchanged). */
 int gpf_set_param(gpf_ctx* ctx, const char* name, double value);
 
 /* Adjoint (reverse mode of the discrete step, hand-written kernels).
@@ -239,15 +275,24 @@ int gpf_adjoint_device(gpf_ctx* ctx, const void* dev_dL_dphi, size_t count, cons
                        int32_t n_names, double* grads_out);
 int gpf_adjoint_state(gpf_ctx* ctx, int32_t field, double* host_dst, size_t count);
 
-/* Step counter n (it sets the time of the pulled temperature field).  The
- * setter is for resuming a checkpoint; n >= 0. */
+/* Step counter n of the time loop of Algorithm phfLBM (App. A); it sets the
+ * time of the pulled temperature T_E + G (x - y0 - V n) of Case 2 (Sec. 3).
+ * The setter is for resuming a checkpoint; n >= 0 (else GPF_ERR_ARG). */
 int64_t gpf_step_index(const gpf_ctx* ctx);
 int gpf_set_step_index(gpf_ctx* ctx, int64_t n);
-/* Cells the moving frame has shifted the fields along the pull axis so far
- * (laboratory coordinate = grid index + offset; the pulled temperature uses
- * it).  The setter is for resuming a checkpoint; offset >= 0. */
+/* Cells the moving frame of Case 2 (Sec. 3) has shifted the fields along the
+ * pull axis so far (laboratory coordinate = grid index + offset; the pulled
+ * temperature uses it).  The setter is for resuming a checkpoint; offset >= 0
+ * (else GPF_ERR_ARG). */
 int64_t gpf_frame_offset(const gpf_ctx* ctx);
 int gpf_set_frame_offset(gpf_ctx* ctx, int64_t offset);
+/* Error reporting and teardown (no operation of the paper).  gpf_last_error:
+ * message of the last failing call on ctx (NULL ctx: of the last failed
+ * gpf_init on this thread); the string belongs to the library and lives
+ * until the next call on ctx.  gpf_status_string: a static name of a
+ * gpf_status.  gpf_destroy: waits for the context's stream, releases every
+ * device buffer (through dev_free when given) and the context; NULL is a
+ * no-op. */
 const char* gpf_last_error(const gpf_ctx* ctx);
 const char* gpf_status_string(int status);
 void gpf_destroy(gpf_ctx* ctx);

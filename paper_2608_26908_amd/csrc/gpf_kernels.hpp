@@ -896,12 +896,13 @@ __global__ void k_derived(KP<R> p, int which, const R* __restrict__ phi, const R
   }
 }
 
-// FP64 block partial sums in a fixed order: solute (NC values) or mass.
+// FP64 block partial sums in a fixed order: solute (NC values, which 0),
+// mass (which 1) or the loss 1/2 sum_a (phi_a - target_a)^2 (which 2).
 constexpr int RED_BLOCK = 256;
 template <int D, int Q, int N, int NC, class R>
 __global__ void __launch_bounds__(RED_BLOCK)
 k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ mu,
-          const R* __restrict__ f, double* __restrict__ partial) {
+          const R* __restrict__ f, const double* __restrict__ target, double* __restrict__ partial) {
   using L = Lat<Q>;
   __shared__ double sh[NC][RED_BLOCK];
   const int t = threadIdx.x;
@@ -923,7 +924,7 @@ k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ m
         }
         acc[i] += c;
       }
-    } else {
+    } else if (which == 1) {
       const int x = (int)(P % p.n[0]);
       const int y = (int)((P / p.sy) % p.n[1]);
       const int z = (int)(P / p.sz);
@@ -931,6 +932,13 @@ k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ m
       for (int k = 0; k < L::Q; ++k)
         r += (double)pull_f<D, Q, R>(p, f, x, y, z, P, k) + L::w(k) * (double)p.rho0;
       acc[0] += r;
+    } else {
+      double r = 0.0;
+      for (int b = 0; b < N; ++b) {
+        const double d = (double)phi[b * p.cells + P] - target[b * p.cells + P];
+        r += d * d;
+      }
+      acc[0] += 0.5 * r;
     }
   }
   for (int i = 0; i < NC; ++i) sh[i][t] = acc[i];
@@ -959,6 +967,14 @@ __global__ void k_final_sum(const double* __restrict__ partial, int nblocks, int
     if (threadIdx.x == 0) out[i] = sh[0];
     __syncthreads();
   }
+}
+
+// dL/dphi of the loss 1/2 sum (phi - target)^2: phi - target in FP64
+template <class R>
+__global__ void k_loss_seed(const R* __restrict__ phi, const double* __restrict__ target,
+                            double* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)phi[i] - target[i];
 }
 
 // health: NaN/Inf in phi or mu, or rho <= 0, records the smallest step seen

@@ -63,6 +63,7 @@ struct gpf_ctx {
   DevBuf bulkf[2];
   bool bulk_ok[2] = {false, false};
   int64_t frame_off = 0;  // moving frame: cells shifted so far along the pull axis
+  const double* target = nullptr;  // loss target (caller's device memory, N * cells FP64)
   const Ops* ops = nullptr;
   std::string err;
   // adjoint: checkpoints every rec_every steps from step rec_start
@@ -222,6 +223,8 @@ struct Ops {
   int (*read)(gpf_ctx*, int, double*);  // to scratch (device FP64), returns components
   int (*write)(gpf_ctx*, int);          // from scratch
   int (*reduce)(gpf_ctx*, int, double*);
+  int (*reduce_dev)(gpf_ctx*, int, double*, double*);  // which, partials, device output
+  int (*loss_seed)(gpf_ctx*, double*);
   int (*read_native)(gpf_ctx*, int, void*);
   int (*adjoint)(gpf_ctx*, const double*, bool, double*);  // seed, seed in device memory, grads
   int (*copy_state)(gpf_ctx*, const StateBuf&, const StateBuf&);
@@ -229,6 +232,11 @@ struct Ops {
 };
 
 inline unsigned lin_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// blocks of the partial-sum kernel of the FP64 totals: at most kRedBlocks
+constexpr int kRedBlocks = 2048;
+inline int reduce_blocks(const gpf_ctx* c) {
+  return (int)std::min<int64_t>(kRedBlocks, lin_blocks(c->cells, gpf::RED_BLOCK));
+}
 // grid of the adjoint kernels: one slab of ceil(ny / 8) rows per XCD (gpf::adj_cell)
 inline unsigned adj_blocks(const int64_t (&n)[3]) {
   return 8u * lin_blocks(n[0] * ((n[1] + 7) / 8) * n[2], gpf::ADJ_BLOCK);
@@ -501,21 +509,36 @@ struct Impl {
     return GPF_OK;
   }
 
-  static int reduce(gpf_ctx* c, int which, double* host_out) {
+  // the fixed-order FP64 total `which` into dev_out (device memory) through
+  // the partial sums in `partial` (reduce_blocks(c) * 2 doubles); asynchronous
+  static int reduce_dev(gpf_ctx* c, int which, double* partial, double* dev_out) {
     gpf::KP<R> k = make_kp<R>(c);
     const int s = c->cur;
-    const int nblk = (int)std::min<int64_t>(2048, lin_blocks(c->cells, gpf::RED_BLOCK));
+    const int nblk = reduce_blocks(c);
     const int ncomp = which == GPF_SUM_SOLUTE ? NC : 1;
     hipLaunchKernelGGL((gpf::k_partial<D, Q, N, NC, R>), dim3(nblk), dim3(gpf::RED_BLOCK), 0, c->stream, k,
-                       which == GPF_SUM_SOLUTE ? 0 : 1, P(c->phi[s]), P(c->mu[s]), P(c->f[s]),
-                       static_cast<double*>(c->partial.ptr));
-    hipLaunchKernelGGL(gpf::k_final_sum, dim3(1), dim3(gpf::RED_BLOCK), 0, c->stream,
-                       static_cast<const double*>(c->partial.ptr), nblk, ncomp,
-                       static_cast<double*>(c->redout.ptr));
+                       which, P(c->phi[s]), P(c->mu[s]), P(c->f[s]), c->target, partial);
+    hipLaunchKernelGGL(gpf::k_final_sum, dim3(1), dim3(gpf::RED_BLOCK), 0, c->stream, partial, nblk, ncomp,
+                       dev_out);
     HIP_OR_FAIL(c, hipGetLastError());
+    return GPF_OK;
+  }
+
+  static int reduce(gpf_ctx* c, int which, double* host_out) {
+    const int ncomp = which == GPF_SUM_SOLUTE ? NC : 1;
+    int rc = reduce_dev(c, which, static_cast<double*>(c->partial.ptr), static_cast<double*>(c->redout.ptr));
+    if (rc) return rc;
     HIP_OR_FAIL(c, hipMemcpyAsync(host_out, c->redout.ptr, ncomp * sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return GPF_OK;
+  }
+
+  static int loss_seed(gpf_ctx* c, double* dev_seed) {
+    const int64_t cnt = (int64_t)N * c->cells;
+    hipLaunchKernelGGL((gpf::k_loss_seed<R>), dim3(lin_blocks(cnt, 256)), dim3(256), 0, c->stream,
+                       P(c->phi[c->cur]), c->target, dev_seed, cnt);
+    HIP_OR_FAIL(c, hipGetLastError());
     return GPF_OK;
   }
 
@@ -837,7 +860,8 @@ struct Impl {
   }
 
   static const Ops* ops() {
-    static const Ops o = {&step, &frame, &read, &write, &reduce, &read_native, &adjoint, &copy_state, &lam_read};
+    static const Ops o = {&step,      &frame,   &read,       &write,      &reduce,  &reduce_dev,
+                          &loss_seed, &read_native, &adjoint, &copy_state, &lam_read};
     return &o;
   }
 };
@@ -1138,7 +1162,7 @@ int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_co
     if (!rc) rc = dev_alloc(c, c->f[s], c->Q * cs);
   }
   if (!rc) rc = dev_alloc(c, c->scratch, (size_t)(c->Q + 1) * c->cells * sizeof(double));
-  if (!rc) rc = dev_alloc(c, c->partial, 2048 * 2 * sizeof(double));
+  if (!rc) rc = dev_alloc(c, c->partial, kRedBlocks * 2 * sizeof(double));
   if (!rc) rc = dev_alloc(c, c->redout, 4 * sizeof(double));
   if (!rc) rc = dev_alloc(c, c->badstep, sizeof(unsigned long long));
   if (!rc) rc = dev_alloc(c, c->frontbuf, sizeof(int));
@@ -1230,8 +1254,31 @@ int gpf_write(gpf_ctx* c, int32_t field, const double* src, size_t count) {
 
 int gpf_reduce(gpf_ctx* c, int32_t which, double* out) {
   if (!c || !out) return GPF_ERR_ARG;
-  if (which != GPF_SUM_SOLUTE && which != GPF_SUM_MASS) return fail(c, GPF_ERR_ARG, "unknown reduction %d", which);
+  if (which != GPF_SUM_SOLUTE && which != GPF_SUM_MASS && which != GPF_LOSS)
+    return fail(c, GPF_ERR_ARG, "unknown reduction %d", which);
+  if (which == GPF_LOSS && !c->target) return fail(c, GPF_ERR_STATE, "GPF_LOSS needs a target (gpf_set_target)");
   return c->ops->reduce(c, which, out);
+}
+
+int gpf_set_target(gpf_ctx* c, const void* dev_target, size_t count) {
+  if (!c) return GPF_ERR_ARG;
+  if (!dev_target) {
+    if (count != 0) return fail(c, GPF_ERR_ARG, "a NULL target clears it and takes count 0");
+    c->target = nullptr;
+    return GPF_OK;
+  }
+  if (count != (size_t)c->N * (size_t)c->cells)
+    return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, (size_t)c->N * (size_t)c->cells);
+  c->target = static_cast<const double*>(dev_target);
+  return GPF_OK;
+}
+
+int gpf_loss_seed_device(gpf_ctx* c, void* dev_seed, size_t count) {
+  if (!c || !dev_seed) return GPF_ERR_ARG;
+  if (count != (size_t)c->N * (size_t)c->cells)
+    return fail(c, GPF_ERR_ARG, "count %zu, expected %zu", count, (size_t)c->N * (size_t)c->cells);
+  if (!c->target) return fail(c, GPF_ERR_STATE, "no loss target (gpf_set_target)");
+  return c->ops->loss_seed(c, static_cast<double*>(dev_seed));
 }
 
 int gpf_set_param(gpf_ctx* c, const char* name, double value) {

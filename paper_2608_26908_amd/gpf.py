@@ -20,6 +20,7 @@ STATUS = {0: "GPF_OK", -1: "GPF_ERR_ARG", -2: "GPF_ERR_PARAM", -3: "GPF_ERR_NOME
           -4: "GPF_ERR_DEVICE", -5: "GPF_ERR_NONFINITE", -6: "GPF_ERR_STATE",
           -7: "GPF_ERR_UNSUPPORTED"}
 FIELDS = {"phi": 0, "mu": 1, "f": 2, "rho": 3, "u": 4, "c": 5, "T": 6, "flags": 7, "fpost": 8}
+REDUCTIONS = {"solute": 0, "mass": 1, "loss": 2}
 PRECISION = {"fp64": 0, "fp32": 1}
 
 
@@ -83,6 +84,8 @@ def lib():
         L.gpf_read_device.argtypes = [vp, i32, vp, ctypes.c_size_t]
         L.gpf_write.argtypes = [vp, i32, dp, ctypes.c_size_t]
         L.gpf_reduce.argtypes = [vp, i32, dp]
+        L.gpf_set_target.argtypes = [vp, vp, ctypes.c_size_t]
+        L.gpf_loss_seed_device.argtypes = [vp, vp, ctypes.c_size_t]
         L.gpf_set_param.argtypes = [vp, ctypes.c_char_p, ctypes.c_double]
         L.gpf_set_step_index.argtypes = [vp, i64]
         L.gpf_step_index.restype = i64
@@ -299,9 +302,30 @@ class Sim:
                                     a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size))
 
     def reduce(self, which):
+        """FP64 total in a fixed order: 'solute' (nc values), 'mass', or
+        'loss' (1/2 sum (phi - target)^2 against set_target's target)."""
         out = (ctypes.c_double * 2)()
-        self._check(lib().gpf_reduce(self._h, {"solute": 0, "mass": 1}[which], out))
+        self._check(lib().gpf_reduce(self._h, REDUCTIONS[which], out))
         return np.array(out[: self.nc]) if which == "solute" else float(out[0])
+
+    def set_target(self, target):
+        """Loss target phi^target (N x grid): kept on the device as FP64 for
+        the context's lifetime or until replaced; None clears it."""
+        if target is None:
+            self._check(lib().gpf_set_target(self._h, None, 0))
+            self._target = None
+            return
+        import torch
+        t = torch.as_tensor(target, dtype=torch.float64, device="cuda").contiguous()
+        self._check(lib().gpf_set_target(self._h, ctypes.c_void_p(t.data_ptr()), t.numel()))
+        self._target = t
+
+    def loss_seed(self):
+        """dL/dphi = phi - target (FP64 tensor on the device) at the current state."""
+        import torch
+        t = torch.empty((self.N,) + self.shape, dtype=torch.float64, device="cuda")
+        self._check(lib().gpf_loss_seed_device(self._h, ctypes.c_void_p(t.data_ptr()), t.numel()))
+        return t
 
     def set_param(self, name, value):
         self._check(lib().gpf_set_param(self._h, name.encode(), float(value)))
@@ -309,6 +333,7 @@ class Sim:
     # -- adjoint -------------------------------------------------------------
     def record(self, checkpoint_every):
         self._check(lib().gpf_record(self._h, int(checkpoint_every)))
+        self.recording = getattr(self, "recording", 0) + 1
 
     def adjoint(self, dL_dphi, names):
         """FP64 dL/dp for the named parameters, given dL/dphi at the current
@@ -337,39 +362,81 @@ class Sim:
         return out.reshape((comps,) + self.shape)
 
 
-def _autograd_function():
+def _forward_run(ctx, params, sim, initial, names, n_steps, checkpoint_every):
+    sim.restore(initial)
+    for name, v in zip(names, params.detach().cpu().tolist()):
+        sim.set_param(name, v)
+    sim.record(checkpoint_every)
+    sim.step(n_steps)
+    ctx.sim, ctx.names = sim, list(names)
+    # the adjoint reverses whatever the context holds: remember which run this is
+    ctx.recording, ctx.step_index = sim.recording, sim.step_index
+    ctx.param_device, ctx.param_dtype = params.device, params.dtype
+
+
+def _check_same_run(ctx):
+    if ctx.sim.recording != ctx.recording or ctx.sim.step_index != ctx.step_index:
+        raise RuntimeError("the simulation was recorded again or stepped since this forward run: "
+                           "its adjoint would be that of another trajectory")
+
+
+def _autograd_functions():
     import torch
 
     class GPFRun(torch.autograd.Function):
         """phi after n_steps of the coupled step as a differentiable function
         of scalar parameters.  forward: restore the initial checkpoint, set
         the parameters, record and run; backward: the hand-written adjoint
-        (gpf_adjoint), FP64 parameter gradients."""
+        (gpf_adjoint_device), FP64 parameter gradients."""
 
         @staticmethod
         def forward(ctx, params, sim, initial, names, n_steps, checkpoint_every):
-            sim.restore(initial)
-            for name, v in zip(names, params.detach().cpu().tolist()):
-                sim.set_param(name, v)
-            sim.record(checkpoint_every)
-            sim.step(n_steps)
-            ctx.sim, ctx.names = sim, list(names)
+            _forward_run(ctx, params, sim, initial, names, n_steps, checkpoint_every)
             return sim.read_device("phi")
 
         @staticmethod
         def backward(ctx, grad_phi):
+            _check_same_run(ctx)
             g = ctx.sim.adjoint(grad_phi, ctx.names)
-            return torch.tensor(g, dtype=torch.float64), None, None, None, None, None
+            return (torch.tensor(g, dtype=ctx.param_dtype, device=ctx.param_device),
+                    None, None, None, None, None)
 
-    return GPFRun
+    class GPFLoss(torch.autograd.Function):
+        """The loss L = 1/2 sum (phi - target)^2 after n_steps (the target set
+        with Sim.set_target), FP64 and computed by the library (GPF_LOSS);
+        backward seeds the adjoint with dL/dphi = phi - target computed on the
+        device (gpf_loss_seed_device)."""
+
+        @staticmethod
+        def forward(ctx, params, sim, initial, names, n_steps, checkpoint_every):
+            _forward_run(ctx, params, sim, initial, names, n_steps, checkpoint_every)
+            return torch.tensor(sim.reduce("loss"), dtype=torch.float64, device=params.device)
+
+        @staticmethod
+        def backward(ctx, grad_loss):
+            _check_same_run(ctx)
+            g = ctx.sim.adjoint(ctx.sim.loss_seed(), ctx.names)
+            g = torch.tensor(g, dtype=ctx.param_dtype, device=ctx.param_device)
+            return g * grad_loss.to(g.device, g.dtype), None, None, None, None, None
+
+    return GPFRun, GPFLoss
 
 
-_GPFRun = None
+_FUNCS = None
 
 
 def gpf_run(params, sim, initial, names, n_steps, checkpoint_every):
-    """Differentiable run (torch.autograd): see GPFRun."""
-    global _GPFRun
-    if _GPFRun is None:
-        _GPFRun = _autograd_function()
-    return _GPFRun.apply(params, sim, initial, tuple(names), n_steps, checkpoint_every)
+    """Differentiable run (torch.autograd): phi after n_steps, see GPFRun."""
+    global _FUNCS
+    if _FUNCS is None:
+        _FUNCS = _autograd_functions()
+    return _FUNCS[0].apply(params, sim, initial, tuple(names), n_steps, checkpoint_every)
+
+
+def gpf_loss(params, sim, initial, names, n_steps, checkpoint_every):
+    """Differentiable loss (torch.autograd): L = 1/2 sum (phi - target)^2
+    after n_steps against sim's target, see GPFLoss."""
+    global _FUNCS
+    if _FUNCS is None:
+        _FUNCS = _autograd_functions()
+    return _FUNCS[1].apply(params, sim, initial, tuple(names), n_steps, checkpoint_every)

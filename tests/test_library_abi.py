@@ -125,3 +125,16 @@ def test_null_context_is_an_argument_error(gpf):
     assert L.gpf_adjoint_state(None, 0, seed, 4) == -1
     assert L.gpf_record(None, 4) == -1
     assert L.gpf_step(None, 1) == -1
+    assert L.gpf_reduce(None, 2, out) == -1
+    assert L.gpf_set_target(None, None, 0) == -1
+    assert L.gpf_loss_seed_device(None, ctypes.c_void_p(1), 4) == -1
+
+
+def test_reduction_enum_has_the_loss():
+    """GPF_LOSS is value 2 of gpf_reduction in the header, as the binding uses it."""
+    from paper_2608_26908_amd.gpf import REDUCTIONS
+    text = open(HEADER).read()
+    m = re.search(r"typedef enum \{([^}]*)\} gpf_reduction;", text)
+    vals = dict((k.strip(), int(v)) for k, v in (e.split("=") for e in m.group(1).split(",")))
+    assert vals == {"GPF_SUM_SOLUTE": 0, "GPF_SUM_MASS": 1, "GPF_LOSS": 2}
+    assert REDUCTIONS == {"solute": 0, "mass": 1, "loss": 2}
