@@ -948,8 +948,11 @@ k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ m
       for (int i = 0; i < NC; ++i) sh[i][t] += sh[i][t + s];
     __syncthreads();
   }
+  // one value per block and component of this total, in the stride
+  // k_final_sum reads: NC for the solute, 1 for the mass and the loss
+  const int ncomp = (which == 0) ? NC : 1;
   if (t == 0)
-    for (int i = 0; i < NC; ++i) partial[blockIdx.x * NC + i] = sh[i][0];
+    for (int i = 0; i < ncomp; ++i) partial[blockIdx.x * ncomp + i] = sh[i][0];
 }
 
 __global__ void k_final_sum(const double* __restrict__ partial, int nblocks, int ncomp,

@@ -1,16 +1,36 @@
-"""The loss of the adjoint inversion inside the library: GPF_LOSS, the FP64
-fixed-order total 1/2 sum (phi - target)^2 against a device target, and its
-seed dL/dphi = phi - target, against the oracle and plain FP64 sums."""
+"""The FP64 totals of the library against the oracle: solute and mass on
+every built instance, and the loss of the adjoint inversion, GPF_LOSS (1/2
+sum (phi - target)^2 against a device target) with its seed dL/dphi = phi -
+target."""
 import ctypes
 
 import numpy as np
 import pytest
 
 from gpu_helpers import gpu_from, oracle_from
-from inputs import busy_config, random_state
+from inputs import KINDS, KINDS4, busy_config, random_state
 from paper_2608_26908_amd.workloads import scaled
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("kind", KINDS + KINDS4)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_totals_match_oracle_every_instance(oracle, kind, precision):
+    """Solute (nc values) and mass totals of a random state on every built
+    instance (one and two solutes, 2D and 3D, three and four phases), FP64
+    sums of the stored values: within 1e-13 of the oracle's totals of the
+    same state (FP32: the stored state is the FP32 rounding of the oracle's,
+    so within 1e-6)."""
+    n = [33, 29] if "2d" in kind else [17, 13, 11]
+    cfg = busy_config(kind, n)
+    st = random_state(cfg, 12)
+    g = gpu_from(cfg, st, precision)
+    o = oracle_from(cfg, st)
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    assert np.allclose(g.reduce("solute"), o.total("solute"), rtol=tol, atol=0)
+    assert g.reduce("mass") == pytest.approx(o.total("mass"), rel=tol)
+    g.close()
 
 
 @pytest.mark.parametrize("kind,n,precision", [("binary2d", [37, 29], "fp64"), ("binary2d", [37, 29], "fp32"),
