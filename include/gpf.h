@@ -207,6 +207,23 @@ int gpf_write(gpf_ctx* ctx, int32_t field, const double* host_src, size_t count)
  * GPF_ERR_STATE (GPF_LOSS without a target), GPF_ERR_DEVICE. */
 int gpf_reduce(gpf_ctx* ctx, int32_t which, double* out);
 
+/* gpf_reduce without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid it): the same totals in the same fixed order
+ * (bitwise those of gpf_reduce), written to caller-owned device memory
+ * dev_out (nc doubles for GPF_SUM_SOLUTE, else one) asynchronously on the
+ * context's stream; no host synchronisation, no allocation, no memset.  The
+ * partial sums live in a static device array of the library (2048 x 2
+ * doubles, 32 KiB, on each GPU it runs on, until the process ends) that
+ * every context on that GPU shares and that holds the last call's partials:
+ * calls that overlap in time on one GPU (other streams, other host threads)
+ * race on it and must be serialised by the caller.  Nothing in it needs
+ * clearing: each call overwrites every partial it reads.  Must be called
+ * with the context's device current.  Errors: GPF_ERR_ARG (NULL, unknown
+ * reduction, more partial sums than the static array holds), GPF_ERR_STATE
+ * (GPF_LOSS without a target, another device current), GPF_ERR_DEVICE. */
+int gpf_reduce_noalloc(gpf_ctx* ctx, int32_t which, double* dev_out);
+
 /* Target phi^target of the loss GPF_LOSS: caller-owned device memory, FP64,
  * N * cells values in the layout of GPF_PHI.  The context keeps the pointer
  * (not the memory): it must stay valid until replaced or cleared (NULL, with

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -64,6 +65,8 @@ struct gpf_ctx {
   bool bulk_ok[2] = {false, false};
   int64_t frame_off = 0;  // moving frame: cells shifted so far along the pull axis
   const double* target = nullptr;  // loss target (caller's device memory, N * cells FP64)
+  int device = 0;                    // HIP device current at gpf_init
+  double* noalloc_partial = nullptr; // this device's address of the static scratch array
   const Ops* ops = nullptr;
   std::string err;
   // adjoint: checkpoints every rec_every steps from step rec_start
@@ -236,6 +239,36 @@ inline unsigned lin_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 constexpr int kRedBlocks = 2048;
 inline int reduce_blocks(const gpf_ctx* c) {
   return (int)std::min<int64_t>(kRedBlocks, lin_blocks(c->cells, gpf::RED_BLOCK));
+}
+
+// gpf_reduce_noalloc keeps its partial sums in this file-scope array instead
+// of the context's buffer: kRedBlocks blocks x 2 components, 32 KiB per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in symbol): it uses the device
+// address that hipGetSymbolAddress returns, resolved once per device.
+constexpr int kNoAllocDoubles = kRedBlocks * 2;
+__device__ __align__(256) double scratch[kNoAllocDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// the current device's address of `scratch` into c (called by gpf_init with
+// the context's device current)
+int resolve_scratch(gpf_ctx* c) {
+  int dev = 0;
+  HIP_OR_FAIL(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, GPF_ERR_DEVICE, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(c, GPF_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  c->device = dev;
+  c->noalloc_partial = g_scratch_dev[dev];
+  return GPF_OK;
 }
 // grid of the adjoint kernels: one slab of ceil(ny / 8) rows per XCD (gpf::adj_cell)
 inline unsigned adj_blocks(const int64_t (&n)[3]) {
@@ -1154,6 +1187,7 @@ int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_co
   c->cells = c->n[0] * c->n[1] * c->n[2];
   c->esize = (params->precision == GPF_FP64) ? 8 : 4;
   c->ops = pick(c->Q, c->N, c->nc, params->precision);
+  rc = resolve_scratch(c);
   const size_t cs = (size_t)c->cells * c->esize;
   for (int s = 0; s < 2 && !rc; ++s) {
     if (!rc) rc = dev_alloc(c, c->phi[s], c->N * cs);
@@ -1258,6 +1292,22 @@ int gpf_reduce(gpf_ctx* c, int32_t which, double* out) {
     return fail(c, GPF_ERR_ARG, "unknown reduction %d", which);
   if (which == GPF_LOSS && !c->target) return fail(c, GPF_ERR_STATE, "GPF_LOSS needs a target (gpf_set_target)");
   return c->ops->reduce(c, which, out);
+}
+
+int gpf_reduce_noalloc(gpf_ctx* c, int32_t which, double* dev_out) {
+  if (!c || !dev_out) return GPF_ERR_ARG;
+  if (which != GPF_SUM_SOLUTE && which != GPF_SUM_MASS && which != GPF_LOSS)
+    return fail(c, GPF_ERR_ARG, "unknown reduction %d", which);
+  if (which == GPF_LOSS && !c->target) return fail(c, GPF_ERR_STATE, "GPF_LOSS needs a target (gpf_set_target)");
+  const int64_t need = (int64_t)reduce_blocks(c) * (which == GPF_SUM_SOLUTE ? c->nc : 1);
+  if (need > kNoAllocDoubles)
+    return fail(c, GPF_ERR_ARG, "%lld partial sums exceed the static scratch of %d doubles", (long long)need,
+                kNoAllocDoubles);
+  int dev = -1;
+  HIP_OR_FAIL(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, GPF_ERR_STATE, "device %d is current, the context lives on device %d", dev, c->device);
+  return c->ops->reduce_dev(c, which, c->noalloc_partial, dev_out);
 }
 
 int gpf_set_target(gpf_ctx* c, const void* dev_target, size_t count) {

@@ -85,6 +85,7 @@ def lib():
         L.gpf_write.argtypes = [vp, i32, dp, ctypes.c_size_t]
         L.gpf_reduce.argtypes = [vp, i32, dp]
         L.gpf_set_target.argtypes = [vp, vp, ctypes.c_size_t]
+        L.gpf_reduce_noalloc.argtypes = [vp, i32, vp]
         L.gpf_loss_seed_device.argtypes = [vp, vp, ctypes.c_size_t]
         L.gpf_set_param.argtypes = [vp, ctypes.c_char_p, ctypes.c_double]
         L.gpf_set_step_index.argtypes = [vp, i64]
@@ -307,6 +308,11 @@ class Sim:
         out = (ctypes.c_double * 2)()
         self._check(lib().gpf_reduce(self._h, REDUCTIONS[which], out))
         return np.array(out[: self.nc]) if which == "solute" else float(out[0])
+
+    def reduce_noalloc(self, which, out):
+        """The total `which` into the FP64 device tensor `out` (nc values for
+        'solute', else one), allocation-free and without synchronising."""
+        self._check(lib().gpf_reduce_noalloc(self._h, REDUCTIONS[which], ctypes.c_void_p(out.data_ptr())))
 
     def set_target(self, target):
         """Loss target phi^target (N x grid): kept on the device as FP64 for
