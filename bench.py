@@ -33,16 +33,37 @@ def bytes_per_lup(cfg, s):
     return 2 * (cfg["N"] - 1 + cfg["nc"] + Q) * s
 
 
-def run_gpu(cfg, precision, steps, warmup, kernel_steps=50):
+def prewarm(sim, min_ms=100.0):
+    """Untimed steps until at least min_ms of device work has run, so that
+    the clocks have left their idle state before the timed window; returns
+    the steps run."""
+    import torch
+    n, done = 1, 0
+    t0 = time.perf_counter()
+    while True:
+        sim.step(n)
+        torch.cuda.synchronize()
+        done += n
+        if (time.perf_counter() - t0) * 1e3 >= min_ms:
+            return done
+        n *= 2
+
+
+def run_gpu(cfg, precision, steps, warmup, kernel_steps=50, advance=0):
     """Throughput over `steps` steps launched back to back (no host
     synchronisation inside the timed region), then the mean duration of each
     kernel over `kernel_steps` more steps, every launch bracketed by HIP events
-    on the library's stream (torch's current stream)."""
+    on the library's stream (torch's current stream).  Before the timed
+    window: `advance` steps (to time a grown microstructure), `warmup` steps
+    and an untimed run of at least 100 ms (clock warm-up)."""
     import torch
     from paper_2608_26908_amd.gpf import Sim
     sim = Sim(cfg, precision=precision)
+    if advance:
+        sim.step(advance)
     sim.step(warmup)
     torch.cuda.synchronize()
+    pre = prewarm(sim)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     t0 = time.perf_counter()
@@ -57,7 +78,7 @@ def run_gpu(cfg, precision, steps, warmup, kernel_steps=50):
     sol = sim.reduce("solute")
     sim.close()
     return dict(ms_per_step=ms / steps, wall_s=wall, cells=cells,
-                k_phi_ms=k_phi_ms / ks, k_mulbm_ms=k_mulbm_ms / ks,
+                k_phi_ms=k_phi_ms / ks, k_mulbm_ms=k_mulbm_ms / ks, prewarm_steps=pre,
                 mlups=cells * steps / (ms * 1e-3) / 1e6, solute=[float(v) for v in sol])
 
 
@@ -81,16 +102,27 @@ def copy_bandwidth(mib=1024, reps=20):
     return 2 * mib * (1 << 20) / (ms * 1e-3) / 1e9
 
 
-def run_adjoint(cfg, precision, steps, K, names):
-    """Wall time of the forward run (recording checkpoints every K steps) and of
-    the reverse sweep (segment recompute + adjoint kernels), same stream; the
-    seed dL/dphi is already in device memory."""
+def run_adjoint(cfg, precision, steps, K, names, target_changes):
+    """Wall time of the forward run and of the reverse sweep (segment
+    recompute + adjoint kernels), same stream, for the loss L = 1/2 sum (phi -
+    phi_t)^2 against a target run with other parameters: the library forms L
+    (GPF_LOSS) and its seed dL/dphi on the device.  The timed sweep is the
+    second one of the same recording: the first allocates the tapes and the
+    adjoint buffers, which later sweeps (an inversion loop) reuse."""
     import torch
     from paper_2608_26908_amd.gpf import Sim
+    t = Sim(dict(cfg, **target_changes), precision=precision)
+    t.step(steps)
+    target = t.read_device("phi").double()
+    t.close()
     sim = Sim(cfg, precision=precision)
+    sim.set_target(target)
     sim.step(2)  # warm-up of every kernel
     torch.cuda.synchronize()
     ck = sim.checkpoint()
+    prewarm(sim)
+    sim.restore(ck)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
@@ -102,16 +134,21 @@ def run_adjoint(cfg, precision, steps, K, names):
     sim.step(steps)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
-    # dL/dphi resident in device memory, as a loss gradient computed on the GPU
-    seed = torch.sin(torch.arange(sim.N * sim.cells, dtype=torch.float64, device="cuda"))
+    loss = sim.reduce("loss")
+    seed = sim.loss_seed()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.adjoint(seed, names)
+    t_cold = time.perf_counter() - t0
     t0 = time.perf_counter()
     grads = sim.adjoint(seed, names)
     t_adj = time.perf_counter() - t0
     sim.close()
     return dict(forward_ms=round(t_plain * 1e3, 2), forward_recording_ms=round(t_fwd * 1e3, 2),
                 adjoint_ms=round(t_adj * 1e3, 2), ratio=round(t_adj / t_plain, 3),
-                grads=dict(zip(names, [float(g) for g in grads])))
+                first_sweep_ms=round(t_cold * 1e3, 2),
+                timed="second reverse sweep of the recording (the first allocated tapes and adjoint buffers)",
+                loss=loss, grads=dict(zip(names, [float(g) for g in grads])))
 
 
 def solute_drift(cfg, precision, steps=10000):
@@ -127,24 +164,46 @@ def solute_drift(cfg, precision, steps=10000):
     return float(np.max(np.abs(s1 - s0) / np.abs(s0)))
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu), or the platform's processor string."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(cfg, steps=7):
-    """The FP64 oracle as it stands, on this host's cores, on a bounded
-    sample of the same workload: the full grid, one untimed step, then
-    `steps` timed steps."""
+    """The FP64 oracle as it stands, on this host's cores, on bounded samples
+    of the same workload: all cores on the full grid (one untimed step, then
+    `steps` timed steps), and one thread on a 128^3 block of it (same
+    parameters, seed at the same relative place; one untimed step, two timed)."""
     from oracle import pyoracle
+    from paper_2608_26908_amd.workloads import cells as ncells, scaled
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     sim = pyoracle.OracleSim(cfg, threads=threads)
     sim.step(1)
     t0 = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t0
-    cells = 1
-    for a in range(cfg["dim"]):
-        cells *= cfg["n"][a]
-    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
+    sub = scaled(cfg["name"], [128] * cfg["dim"])
+    one = pyoracle.OracleSim(sub, threads=1)
+    one.step(1)
+    t1 = time.perf_counter()
+    one.step(2)
+    dt1 = time.perf_counter() - t1
+    return {"value": round(ncells(cfg) * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"full {cfg['n']} grid, FP64 oracle, {steps} timed steps after 1 untimed step "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s)",
+            "one_thread": {"value": round(ncells(sub) * 2 / dt1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                           "sample": f"{sub['n']} block of the workload, 2 timed steps after 1 untimed "
+                                     f"({dt1:.1f} s)"}}
 
 
 def traffic_record(name, precision):
@@ -203,6 +262,12 @@ def main():
     print(f"# fp32: {r32['mlups']:.1f} MLUPS, {r32['ms_per_step']:.3f} ms/step "
           f"(k_phi {r32['k_phi_ms']:.3f} ms, k_mulbm {r32['k_mulbm_ms']:.3f} ms)", file=sys.stderr,
           flush=True)
+    # the same workload grown: the dendrite after its 5000 configured steps
+    late = None
+    if not args.no_extra:
+        late = run_gpu(cfg, "fp32", args.steps, args.warmup, advance=cfg.get("steps", 5000))
+        print(f"# fp32 after {cfg.get('steps', 5000)} steps: {late['mlups']:.1f} MLUPS, "
+              f"{late['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
         r64 = run_gpu(cfg, "fp64", args.steps, args.warmup)
@@ -266,7 +331,16 @@ def main():
                      "step_frac": round(b32 * cells / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "copy_GBps": round(copy_gbs, 1)},
         "kernels_ms": {"k_phi": round(r32["k_phi_ms"], 4), "k_mulbm": round(r32["k_mulbm_ms"], 4)},
+        "timing": f"{args.warmup} warm-up steps, then an untimed run of {r32['prewarm_steps']} steps "
+                  "(>= 100 ms of device work) before the timed window",
     }
+    if late:
+        line["grown"] = {"workload": f"{args.workload} after its {cfg.get('steps', 5000)} configured steps "
+                                     "(grown dendrite)", "value": round(late["mlups"], 2), "unit": "MLUPS",
+                         "ms_per_step": round(late["ms_per_step"], 4),
+                         "k_phi_ms": round(late["k_phi_ms"], 4), "k_mulbm_ms": round(late["k_mulbm_ms"], 4),
+                         "roofline_frac": round(b32 * cells / (late["k_mulbm_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "step_frac": round(b32 * cells / (late["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if not args.no_extra:
         line["shrinkage"] = {"value": round(rs["mlups"], 2), "unit": "MLUPS", "eta": [0.2, 0.0, 0.0],
                              "ms_per_step": round(rs["ms_per_step"], 4),
@@ -299,14 +373,16 @@ def main():
         line["adjoint"] = dict(
             workload="adjoint2d: 256x256 D2Q9 dendrite, FP32 forward, FP64 gradients, 2000 steps, "
                      "checkpoint every 100",
-            **run_adjoint(a2, "fp32", 2000, 100, ["delta", "tau_pf", "D", "gbeta"]))
+            **run_adjoint(a2, "fp32", 2000, 100, ["delta", "tau_pf", "D", "gbeta"],
+                          dict(delta=[[0, 0.025], [0.025, 0]], tau_pf=1.2, gbeta=[2e-5])))
         print(f"# adjoint2d: ratio {line['adjoint']['ratio']}", file=sys.stderr, flush=True)
         e3 = workload("eutectic3d")
         line["adjoint3d"] = dict(
             workload="eutectic3d: 192x192x384 D3Q19, 3 phases, 2 solutes, FP32 forward, 1000 steps (a tenth "
                      "of the 10^4-step run), checkpoint every 100 (the interval that fits the whole run's "
                      "checkpoints and two tapes in 288 GB)",
-            **run_adjoint(e3, "fp32", 1000, 100, ["D", "D1"]))
+            **run_adjoint(e3, "fp32", 1000, 100, ["D", "D1"],
+                          dict(D=[[0.0, 0.0], [0.0, 0.0], [1.2, 0.8]])))
         print(f"# adjoint3d: ratio {line['adjoint3d']['ratio']}", file=sys.stderr, flush=True)
     if not args.no_extra:
         # every workload of the paper's configurations, FP32 and FP64 side by
