@@ -181,44 +181,60 @@ def test_autograd_function_and_descent(oracle):
     assert min(later) < l0, (l0, later)
 
 
-def test_adjoint_large_grid_against_central_differences():
+def test_adjoint_large_grid_against_oracle_complex_step(oracle):
     """Grids of more than 256 * 4 * 4 * 64 cells run the gather and the LBM
-    reverse of the next step as separate launches (smaller grids share one).
-    FP64 gradients there against central differences (h = 1e-6 relative) of
-    the library's own FP64 forward, whose parity with the oracle the forward
-    tests establish: the 3D ternary eutectic (periodic x, y; three phases, two
-    solutes) on 72 x 72 x 64 cells, 6 steps, a checkpoint every 3."""
+    reverse of the next step as separate launches and the flux VJPs as one
+    grid (smaller grids fuse and split them): the path the eutectic3d adjoint
+    benchmark times.  FP64 gradients there against the oracle's complex-step
+    derivatives (exact to round-off away from the projection's kinks) on the
+    3D ternary eutectic (periodic x, y; three phases, two solutes), 72 x 72 x
+    64 cells, 6 steps, a checkpoint every 3, target from the oracle run with
+    other diffusivities and relaxation."""
     from paper_2608_26908_amd.gpf import Sim
     cfg = scaled("eutectic3d", [72, 72, 64], lam_height=12.0, y0=12.0)
     assert 72 * 72 * 64 > 256 * 4 * 4 * 64
     steps, K = 6, 3
-    base = {"D": 1.0, "D1": 1.0, "tau_pf": float(cfg["tau_pf"])}
-    t = Sim(dict(cfg, D=[[0.0, 0.0], [0.0, 0.0], [1.3, 0.8]], tau_pf=1.1 * base["tau_pf"]), precision="fp64")
+    t = oracle.OracleSim(dict(cfg, D=[[0.0, 0.0], [0.0, 0.0], [1.3, 0.8]], tau_pf=1.1 * cfg["tau_pf"]))
     t.step(steps)
-    target = t.read("phi")
-    t.close()
+    target = t.get("phi")
+    del t
     g = Sim(cfg, precision="fp64")
-    ck = g.checkpoint()
     g.record(K)
     g.step(steps)
     phi = g.read("phi")
-    names = list(base)
+    names = ["D", "D1", "tau_pf"]
     grads = g.adjoint(phi - target, names)
-
-    def loss(name, v):
-        g.restore(ck)
-        g.set_param(name, v)
-        g.step(steps)
-        out = 0.5 * float(((g.read("phi") - target) ** 2).sum())
-        g.set_param(name, base[name])
-        return out
-
-    h = 1e-6
-    for name, gv in zip(names, grads):
-        v = base[name]
-        fd = (loss(name, v * (1 + h)) - loss(name, v * (1 - h))) / (2 * h * v)
-        assert gv == pytest.approx(fd, rel=1e-5), (name, gv, fd)
     g.close()
+    o = oracle.OracleSim(cfg)
+    for name, gv in zip(names, grads):
+        loss, ref = o.loss_grad_cs(steps, target, name)
+        assert loss == pytest.approx(0.5 * float(((phi - target) ** 2).sum()), rel=1e-12)
+        assert gv == pytest.approx(ref, rel=1e-8), (name, gv, ref)
+
+
+def test_adjoint_dot_product_large_grid(oracle):
+    """The dot-product identity <w, J v> = <J^T w, v> on a grid above the
+    fusion threshold (the separate gather and LBM-reverse launches), J v from
+    the oracle's complex-step tangent, for perturbations of phi, mu, U and f:
+    3D ternary with two solutes, 72 x 72 x 64, 4 steps over two segments."""
+    cfg = busy_config("ternary3d_nc2", [72, 72, 64])
+    assert 72 * 72 * 64 > 256 * 4 * 4 * 64
+    st = random_state(cfg, 31)
+    steps, K = 4, 2
+    g = gpu_from(cfg, st, "fp64")
+    g.record(K)
+    g.step(steps)
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal((cfg["N"],) + g.shape)
+    g.adjoint(w, [])
+    lam = {field: g.adjoint_state(field) for field in ("phi", "mu", "u", "f")}
+    g.close()
+    o = oracle_from(cfg, st)
+    for field in ("phi", "mu", "u", "f"):
+        v = rng.standard_normal(lam[field].shape)
+        t = o.tangent_cs(steps, field, v, "phi")
+        lhs, rhs = float((w * t).sum()), float((lam[field] * v).sum())
+        assert abs(lhs - rhs) <= 1e-9 * max(abs(lhs), abs(rhs), 1e-30), (field, lhs, rhs)
 
 
 def test_one_tape_when_the_second_does_not_fit():
