@@ -301,6 +301,16 @@ def main():
               flush=True)
     copy_gbs = copy_bandwidth()
     print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    # the achievable side of the roofline: the population update's access
+    # patterns without its arithmetic, on the same grid (library kernels)
+    from paper_2608_26908_amd.gpf import bandwidth_probe
+    ceil, bufs = {}, None
+    for pat in ("copy19", "pull19", "pull19_zmarch"):
+        ceil[pat], a, b = bandwidth_probe(pat, cfg["n"], reps=20, buffers=bufs)
+        bufs = (a, b)
+    del bufs, a, b
+    print(f"# access-pattern ceilings (GB/s): " + ", ".join(f"{k} {v:.0f}" for k, v in ceil.items()),
+          file=sys.stderr, flush=True)
     b32 = bytes_per_lup(cfg, 4)
     cells = r32["cells"]
     achieved = b32 * cells / (r32["k_mulbm_ms"] * 1e-3) / 1e9
@@ -329,7 +339,8 @@ def main():
                      "kernel": "k_mulbm_z (chemical potential + LBM collide/stream, z-marching)",
                      "bytes_per_lup": b32,
                      "step_frac": round(b32 * cells / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "copy_GBps": round(copy_gbs, 1)},
+                     "copy_GBps": round(copy_gbs, 1),
+                     "pattern_ceilings_GBps": {k: round(v, 1) for k, v in ceil.items()}},
         "kernels_ms": {"k_phi": round(r32["k_phi_ms"], 4), "k_mulbm": round(r32["k_mulbm_ms"], 4)},
         "timing": f"{args.warmup} warm-up steps, then an untimed run of {r32['prewarm_steps']} steps "
                   "(>= 100 ms of device work) before the timed window",

@@ -224,6 +224,21 @@ int gpf_reduce(gpf_ctx* ctx, int32_t which, double* out);
  * (GPF_LOSS without a target, another device current), GPF_ERR_DEVICE. */
 int gpf_reduce_noalloc(gpf_ctx* ctx, int32_t which, double* dev_out);
 
+/* Measurement, no operation of the paper: the bandwidth (read + write GB/s)
+ * that the access pattern of the population update reaches without its
+ * arithmetic, the achievable side of the HBM roofline beside the published
+ * peak.  pattern 0: copy of 19 FP32 arrays; 1: the D3Q19 pull out_k(P) =
+ * in_k(P - c_k) (all axes periodic), one thread per cell; 2: the same pull in
+ * the launch shape of the step's dominant kernel (64 x 4 tiles walking 4
+ * planes).  dev_in, dev_out: caller-owned device buffers of 19 * n[0] * n[1]
+ * * n[2] floats each, layout [k][z][y][x]; out is overwritten with the copied
+ * or pulled values.  n[0] a multiple of 64, n[1] and n[2] multiples of 4.
+ * Two untimed launches, then `reps` launches timed with HIP events on
+ * `stream` (a hipStream_t; NULL: the null stream).  Synchronises.  Errors:
+ * GPF_ERR_ARG (NULL, pattern, sizes), GPF_ERR_DEVICE. */
+int gpf_bandwidth_probe(int32_t pattern, const void* dev_in, void* dev_out, const int64_t* n, int32_t reps,
+                        void* stream, double* gbps);
+
 /* Target phi^target of the loss GPF_LOSS: caller-owned device memory, FP64,
  * N * cells values in the layout of GPF_PHI.  The context keeps the pointer
  * (not the memory): it must stay valid until replaced or cleared (NULL, with

@@ -980,6 +980,55 @@ __global__ void k_loss_seed(const R* __restrict__ phi, const double* __restrict_
   if (i < n) out[i] = (double)phi[i] - target[i];
 }
 
+// ---------------------------------------------------------------------------
+// Bandwidth probes (measurement only): the memory access patterns of the
+// population update without its arithmetic, on 19 FP32 arrays of an
+// n0 x n1 x n2 grid (all axes periodic).  k_probe_copy19: out_k(P) = in_k(P);
+// k_probe_pull19: out_k(P) = in_k(P - c_k) with the D3Q19 velocities, one
+// thread per cell in 256-cell blocks; k_probe_pull19_z: the same pull in the
+// launch shape of k_mulbm_z (64 x TY tiles walking ZC planes, XCD-aware tile
+// order).  Streaming (nontemporal) loads and stores as in the step kernels.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_probe_copy19(const float* __restrict__ in, float* __restrict__ out,
+                                                      int64_t cells) {
+  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (P >= cells) return;
+#pragma unroll
+  for (int k = 0; k < 19; ++k)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(&in[k * cells + P]), &out[k * cells + P]);
+}
+
+__device__ __forceinline__ void probe_pull_cell(const float* __restrict__ in, float* __restrict__ out, int x, int y,
+                                                int z, int n0, int n1, int n2, int64_t cells) {
+  using L = Lat<19>;
+  const int64_t P = ((int64_t)z * n1 + y) * n0 + x;
+  float v[19];
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const int xs = (x - L::c(k, 0) + n0) % n0, ys = (y - L::c(k, 1) + n1) % n1, zs = (z - L::c(k, 2) + n2) % n2;
+    v[k] = __builtin_nontemporal_load(&in[k * cells + ((int64_t)zs * n1 + ys) * n0 + xs]);
+  }
+#pragma unroll
+  for (int k = 0; k < 19; ++k) __builtin_nontemporal_store(v[k], &out[k * cells + P]);
+}
+
+__global__ void __launch_bounds__(256) k_probe_pull19(const float* __restrict__ in, float* __restrict__ out, int n0,
+                                                      int n1, int n2) {
+  const int64_t cells = (int64_t)n0 * n1 * n2;
+  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (P >= cells) return;
+  probe_pull_cell(in, out, (int)(P % n0), (int)((P / n0) % n1), (int)(P / ((int64_t)n0 * n1)), n0, n1, n2, cells);
+}
+
+template <int TY>
+__global__ void __launch_bounds__(64 * TY) k_probe_pull19_z(const float* __restrict__ in, float* __restrict__ out,
+                                                            int n0, int n1, int n2, int zc) {
+  const int64_t cells = (int64_t)n0 * n1 * n2;
+  const Tile T = tile_of(n0 / 64, n1 / TY, 64, TY, zc, n2, 3);
+  const int x = T.x0 + (int)threadIdx.x % 64, y = T.y0 + (int)threadIdx.x / 64;
+  for (int z = T.z0; z < T.z1; ++z) probe_pull_cell(in, out, x, y, z, n0, n1, n2, cells);
+}
+
 // health: NaN/Inf in phi or mu, or rho <= 0, records the smallest step seen
 template <int D, int Q, int N, int NC, class R>
 __global__ void k_health(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu,

@@ -1310,6 +1310,46 @@ int gpf_reduce_noalloc(gpf_ctx* c, int32_t which, double* dev_out) {
   return c->ops->reduce_dev(c, which, c->noalloc_partial, dev_out);
 }
 
+int gpf_bandwidth_probe(int32_t pattern, const void* dev_in, void* dev_out, const int64_t* n, int32_t reps,
+                        void* stream, double* gbps) {
+  if (!dev_in || !dev_out || !n || !gbps || reps < 1 || pattern < 0 || pattern > 2) return GPF_ERR_ARG;
+  if (n[0] < 64 || n[0] % 64 || n[1] < kTileY || n[1] % kTileY || n[2] < kZChunkMu || n[2] % kZChunkMu ||
+      n[0] > (1 << 20) || n[1] > (1 << 20) || n[2] > 65535)
+    return GPF_ERR_ARG;
+  const int64_t cells = n[0] * n[1] * n[2];
+  if (19 * cells >= ((int64_t)1 << 31) * 8) return GPF_ERR_ARG;
+  const float* in = static_cast<const float*>(dev_in);
+  float* out = static_cast<float*>(dev_out);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int n0 = (int)n[0], n1 = (int)n[1], n2 = (int)n[2];
+  const unsigned zblocks = (unsigned)((n0 / 64) * (n1 / kTileY) * (n2 / kZChunkMu));
+  auto launch = [&]() {
+    if (pattern == 0)
+      hipLaunchKernelGGL(gpf::k_probe_copy19, dim3(lin_blocks(cells, 256)), dim3(256), 0, st, in, out, cells);
+    else if (pattern == 1)
+      hipLaunchKernelGGL(gpf::k_probe_pull19, dim3(lin_blocks(cells, 256)), dim3(256), 0, st, in, out, n0, n1, n2);
+    else
+      hipLaunchKernelGGL((gpf::k_probe_pull19_z<kTileY>), dim3(zblocks), dim3(64 * kTileY), 0, st, in, out, n0, n1,
+                         n2, kZChunkMu);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return GPF_ERR_DEVICE;
+  launch();
+  launch();
+  (void)hipEventRecord(e0, st);
+  for (int r = 0; r < reps; ++r) launch();
+  (void)hipEventRecord(e1, st);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess || !(ms > 0.f)) return GPF_ERR_DEVICE;
+  *gbps = 2.0 * 19.0 * 4.0 * (double)cells * reps / (ms * 1e-3) / 1e9;
+  return GPF_OK;
+}
+
 int gpf_set_target(gpf_ctx* c, const void* dev_target, size_t count) {
   if (!c) return GPF_ERR_ARG;
   if (!dev_target) {

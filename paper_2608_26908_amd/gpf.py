@@ -86,6 +86,7 @@ def lib():
         L.gpf_reduce.argtypes = [vp, i32, dp]
         L.gpf_set_target.argtypes = [vp, vp, ctypes.c_size_t]
         L.gpf_reduce_noalloc.argtypes = [vp, i32, vp]
+        L.gpf_bandwidth_probe.argtypes = [i32, vp, vp, ctypes.POINTER(i64), i32, vp, dp]
         L.gpf_loss_seed_device.argtypes = [vp, vp, ctypes.c_size_t]
         L.gpf_set_param.argtypes = [vp, ctypes.c_char_p, ctypes.c_double]
         L.gpf_set_step_index.argtypes = [vp, i64]
@@ -446,3 +447,27 @@ def gpf_loss(params, sim, initial, names, n_steps, checkpoint_every):
     if _FUNCS is None:
         _FUNCS = _autograd_functions()
     return _FUNCS[1].apply(params, sim, initial, tuple(names), n_steps, checkpoint_every)
+
+
+PROBES = {"copy19": 0, "pull19": 1, "pull19_zmarch": 2}
+
+
+def bandwidth_probe(pattern, n, reps=20, buffers=None):
+    """Read + write GB/s of an access pattern of the population update
+    without its arithmetic (gpf_bandwidth_probe): 'copy19', 'pull19' (one
+    thread per cell) or 'pull19_zmarch' (the dominant kernel's launch shape),
+    on an n[0] x n[1] x n[2] FP32 grid; buffers: (in, out) torch tensors of
+    19 * cells floats each (allocated when None).  Returns (GB/s, in, out)."""
+    import torch
+    cells = int(n[0]) * int(n[1]) * int(n[2])
+    if buffers is None:
+        buffers = (torch.randn(19 * cells, device="cuda"), torch.empty(19 * cells, device="cuda"))
+    a, b = buffers
+    nn = (ctypes.c_int64 * 3)(*[int(v) for v in n])
+    out = ctypes.c_double()
+    rc = lib().gpf_bandwidth_probe(PROBES[pattern], ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                   nn, int(reps), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                   ctypes.byref(out))
+    if rc != GPF_OK:
+        raise GPFError(rc, "gpf_bandwidth_probe")
+    return out.value, a, b

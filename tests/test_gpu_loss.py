@@ -108,3 +108,22 @@ def test_loss_autograd_equals_the_adjoint_and_guards_the_run(oracle):
     with pytest.raises(RuntimeError, match="stepped"):
         loss.backward()
     sim.close()
+
+
+@pytest.mark.parametrize("pattern", ["copy19", "pull19", "pull19_zmarch"])
+def test_bandwidth_probe_moves_the_right_values(pattern):
+    """The probe kernels copy or pull exactly: out_k = in_k shifted by the
+    D3Q19 velocity c_k (periodic), whatever launch shape times them."""
+    import torch
+    from paper_2608_26908_amd.gpf import bandwidth_probe
+    n = (128, 12, 8)
+    gbps, a, b = bandwidth_probe(pattern, n, reps=2)
+    assert gbps > 0
+    c = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                  [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1],
+                  [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+    fin = a.cpu().numpy().reshape(19, n[2], n[1], n[0])
+    fout = b.cpu().numpy().reshape(19, n[2], n[1], n[0])
+    for k in range(19):
+        want = fin[k] if pattern == "copy19" else np.roll(fin[k], shift=(c[k, 2], c[k, 1], c[k, 0]), axis=(0, 1, 2))
+        assert np.array_equal(fout[k], want), k
