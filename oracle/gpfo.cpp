@@ -116,7 +116,7 @@ struct Par {
   int dim, N, nc, potential, periodic[3], pull_axis, grav_axis, grav_sign;
   long n[3];
   S dx, dt, eps, tau_pf, gamma[NP][NP], delta[NP][NP], chi[2][2], c0[NP][2], dS[NP], T_E, T_iso,
-      D[NP][2], G, V, y0, tau_lb, rho0, gbeta[2], c_ref[2], h_drag, W0, lid_u, eta[NP];
+      D[NP][2], G, V, y0, tau_lb, rho0, gbeta[2], c_ref[2], h_drag, W0, lid_u, eta[NP], mT[NP][2];
   long frame_every, frame_front;
 };
 
@@ -167,6 +167,8 @@ Par<S> lift(const gpfo_params& p) {
   q.W0 = p.W0;
   q.lid_u = p.lid_u;
   for (int a = 0; a < NP; ++a) q.eta[a] = p.eta[a];
+  for (int a = 0; a < NP; ++a)
+    for (int i = 0; i < 2; ++i) q.mT[a][i] = p.mT[a][i];
   q.frame_every = (long)p.frame_every;
   q.frame_front = (long)p.frame_front;
   return q;
@@ -274,23 +276,28 @@ void project_simplex(int m, const S* v, S* out) {
 }
 
 /* grand potential density of phase a (parabolic reading of the thermodynamics):
- * psi^a(mu, T) = -1/2 mu.chi.mu - mu.c0[a] + dS[a] (T - T_E);
- * it satisfies -d psi^a / d mu = C^a(mu) = c0[a] + chi mu. */
+ * psi^a(mu, T) = -1/2 mu.chi.mu - mu.c0_a(T) + dS[a] (T - T_E), with the
+ * parabola centre c0_a(T) = c0[a] + mT[a] (T - T_E): the equilibrium
+ * composition of phase a moving along its coexistence line of App. B, whose
+ * slopes are read as dc/dT (a slope 0 then means a composition independent
+ * of T; read as dT/dc, a 0 would be an infinite rate).  It satisfies
+ * -d psi^a / d mu = C^a(mu, T) = c0_a(T) + chi mu. */
 template <class S>
 S psi(const Par<S>& p, int a, const S* mu, S T) {
   S r = S(0.0);
   for (int i = 0; i < p.nc; ++i) {
     S chimu = 0;
     for (int j = 0; j < p.nc; ++j) chimu += p.chi[i][j] * mu[j];
-    r += -S(0.5) * mu[i] * chimu - mu[i] * p.c0[a][i];
+    r += -S(0.5) * mu[i] * chimu - mu[i] * (p.c0[a][i] + p.mT[a][i] * (T - p.T_E));
   }
   return r + p.dS[a] * (T - p.T_E);
 }
 
+/* composition of phase a at (mu, T): C^a = c0[a] + mT[a] (T - T_E) + chi mu */
 template <class S>
-void comp_C(const Par<S>& p, int a, const S* mu, S* C) {
+void comp_C(const Par<S>& p, int a, const S* mu, S T, S* C) {
   for (int i = 0; i < p.nc; ++i) {
-    C[i] = p.c0[a][i];
+    C[i] = p.c0[a][i] + p.mT[a][i] * (T - p.T_E);
     for (int j = 0; j < p.nc; ++j) C[i] += p.chi[i][j] * mu[j];
   }
 }
@@ -519,14 +526,16 @@ void pf_rhs(const Grid& g, const Par<S>& p, const State<S>& st, const long* x, l
 }
 
 /* ---------------- S4: chemical potential ----------------------------------- */
-/* Eq. (conc) in flux form, with C^a affine in mu (so dC/dT = 0 and the dT/dt
- * term vanishes):
- *   chi_tot = sum_a h_a(phi^{n+1}) chi,   c*(P) = sum_a h_a(phi^{n+1}) C^a(mu^n),
+/* Eq. (conc) in flux form, with C^a affine in mu and T:
+ *   chi_tot = sum_a h_a(phi^{n+1}) chi,   c*(P) = sum_a h_a(phi^{n+1}) C^a(mu^n, T^n),
  *   M(P) = sum_a phi^{n+1}_a diag(D_a) chi,
  *   face P|Q:  J = -(M_P + M_Q)/2 (mu_Q - mu_P)/dx
  *                  + (U_P + U_Q)_a/2 (dx/dt) (c*_P + c*_Q)/2      (0 on walls)
- *   Delta = -dt div J - sum_a C^a(mu^n) (h_a^{n+1} - h_a^n)
+ *   Delta = -dt div J - sum_a C^a(mu^n, T^n) (h_a^{n+1} - h_a^n)
+ *           - sum_a h_a^{n+1} (C^a(mu^n, T^{n+1}) - C^a(mu^n, T^n))
  *   mu^{n+1} = mu^n + chi_tot^{-1} Delta.
+ * The last term is the dT/dt term of Eq. (conc) over one step; with C^a
+ * affine in mu it makes sum_a h_a C^a(mu, T) change exactly by -dt div J.
  * U is the lattice velocity of the previous step (U = 0 in solid cells),
  * converted to phase-field units by dx/dt (one LBM step per PF step). */
 template <class S>
@@ -540,13 +549,16 @@ void mu_cell(const Grid& g, const Par<S>& p, const State<S>& st, const std::vect
     interp_h(N, ph, h, dh);
     S mu[2];
     for (int i = 0; i < nc; ++i) mu[i] = st.mu[i * cells + j];
+    long xj[3];
+    g.coords(j, xj);
+    const S Tj = temperature(p, xj, st.step, st.shift);
     for (int i = 0; i < nc; ++i) {
       cstar[i] = 0;
       for (int k = 0; k < nc; ++k) M[i * nc + k] = 0;
     }
     for (int a = 0; a < N; ++a) {
       S C[2];
-      comp_C(p, a, mu, C);
+      comp_C(p, a, mu, Tj, C);
       for (int i = 0; i < nc; ++i) {
         cstar[i] += h[a] * C[i];
         for (int k = 0; k < nc; ++k) M[i * nc + k] += ph[a] * p.D[a][i] * p.chi[i][k];
@@ -587,12 +599,15 @@ void mu_cell(const Grid& g, const Par<S>& p, const State<S>& st, const std::vect
   interp_h(N, ph0, h0, dh);
   interp_h(N, ph1, h1, dh);
   for (int i = 0; i < nc; ++i) mu[i] = st.mu[i * cells + P];
+  const S T0 = temperature(p, x, st.step, st.shift), T1 = temperature(p, x, st.step + 1, st.shift);
   S Delta[2];
   for (int i = 0; i < nc; ++i) Delta[i] = -p.dt * divJ[i];
   for (int a = 0; a < N; ++a) {
-    S C[2];
-    comp_C(p, a, mu, C);
+    S C[2], C1[2];
+    comp_C(p, a, mu, T0, C);
+    comp_C(p, a, mu, T1, C1);
     for (int i = 0; i < nc; ++i) Delta[i] -= C[i] * (h1[a] - h0[a]);
+    for (int i = 0; i < nc; ++i) Delta[i] -= h1[a] * (C1[i] - C[i]);
   }
   S sh = 0;
   for (int a = 0; a < N; ++a) sh += h1[a];
@@ -648,7 +663,7 @@ void shrinkage_force(const Grid& g, const Par<S>& p, const std::vector<S>& phi_o
  * F = F_E + G_D;  f* = f - (f - f^eq)/tau + Guo source. */
 template <class S>
 void collide_cell(const Lattice& L, const Par<S>& p, const S* fin, S phil,
-                  const S* mu_new, const S* GS, S* fout, S* u_out) {
+                  const S* mu_new, S T1, const S* GS, S* fout, S* u_out) {
   const int d = p.dim;
   S rho = 0, m[3] = {0, 0, 0};
   for (int k = 0; k < L.Q; ++k) {
@@ -656,7 +671,7 @@ void collide_cell(const Lattice& L, const Par<S>& p, const S* fin, S phil,
     for (int a = 0; a < d; ++a) m[a] += fin[k] * S((double)L.c[k][a]);
   }
   S Cl[2];
-  comp_C(p, p.N - 1, mu_new, Cl);
+  comp_C(p, p.N - 1, mu_new, T1, Cl);
   S b = 0;
   for (int i = 0; i < p.nc; ++i) b += p.gbeta[i] * (Cl[i] - p.c_ref[i]);
   S FB[3] = {0, 0, 0};
@@ -734,7 +749,8 @@ void step_once(const Grid& g, const Lattice& L, const Par<S>& p, State<S>& st) {
     shrinkage_force(g, p, st.phi, phin, x, GS);
     for (int k = 0; k < Q; ++k) fin[k] = st.f[k * cells + P];
     for (int i = 0; i < nc; ++i) mnew[i] = mun[i * cells + P];
-    collide_cell(L, p, fin, phin[(N - 1) * cells + P], mnew, GS, fo, uo);
+    collide_cell(L, p, fin, phin[(N - 1) * cells + P], mnew, temperature(p, x, st.step + 1, st.shift), GS, fo,
+                 uo);
     for (int k = 0; k < Q; ++k) fpost[k * cells + P] = fo[k];
     for (int a = 0; a < d; ++a) un[a * cells + P] = uo[a];
   }
@@ -998,10 +1014,13 @@ int gpfo_get(const gpfo_sim* s, int32_t field, double* dst) {
         for (int a = 0; a < p.N; ++a) ph[a] = st.phi[a * cells + P];
         for (int i = 0; i < p.nc; ++i) mu[i] = st.mu[i * cells + P];
         interp_h(p.N, ph, h, dh);
+        long x[3];
+        s->g.coords(P, x);
+        const double T = temperature(p, x, st.step, st.shift);
         for (int i = 0; i < p.nc; ++i) dst[i * cells + P] = 0;
         for (int a = 0; a < p.N; ++a) {
           double C[2];
-          comp_C(p, a, mu, C);
+          comp_C(p, a, mu, T, C);
           for (int i = 0; i < p.nc; ++i) dst[i * cells + P] += h[a] * C[i];
         }
       }
@@ -1115,7 +1134,7 @@ int gpfo_grand_potential(const gpfo_params* prm, int32_t a, const double* mu, do
   cplx m[2];
   for (int j = 0; j < prm->nc; ++j) m[j] = cplx(mu[j]);
   *dpsi_dT = psi(pc, a, m, cplx(T, h)).imag() / h;
-  comp_C(pd, a, mu, conc);
+  comp_C(pd, a, mu, T, conc);
   return 0;
 }
 

@@ -75,6 +75,10 @@ typedef struct {
    * (largest pull-axis index of a cell with phi_liq <= 1/2) lies beyond
    * frame_front, every field is shifted down the pull axis by the excess */
   int64_t frame_every, frame_front;
+  /* temperature dependence of the equilibrium compositions: the parabola
+   * centre of phase a is c0[a] + mT[a] (T - T_E) (App. B coexistence-line
+   * slopes read as dc/dT); all 0: compositions independent of T */
+  double mT[4][2];
 } gpfo_params;
 
 typedef struct gpfo_sim gpfo_sim;

@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
         ("lam_height", ctypes.c_double), ("mu_inf", ctypes.c_double * 2),
         ("noise_sigma", ctypes.c_double), ("eta", ctypes.c_double * 4),
         ("lattice_q", ctypes.c_int32), ("frame_every", ctypes.c_int64),
-        ("frame_front", ctypes.c_int64),
+        ("frame_front", ctypes.c_int64), ("mT", (ctypes.c_double * 2) * 4),
     ]
 
 
@@ -151,6 +151,7 @@ def make_params(cfg):
     _fill(p.init_center, cfg.get("init_center", [0, 0, 0]), (3,))
     _fill(p.mu_inf, cfg["mu_inf"], (2,))
     _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]), (4,))
+    _fill(p.mT, cfg.get("mT", [[0.0, 0.0]] * 4), (4, 2))
     p.lattice_q = 27 if cfg.get("lattice") == "D3Q27" else 0
     p.frame_every = int(cfg.get("frame_every", 0))
     p.frame_front = int(cfg.get("frame_front", 0))

@@ -10,9 +10,16 @@ to synthetic grids.  Where the paper is silent the value is a stated reading:
     C^a(mu) = c0[a] + chi mu; a binary dendrite has c0 = (k, 1) so that the
     equilibrium chemical potential is 0, and a far-field supersaturation
     Delta ("undercooling") gives mu_inf = -Delta (1 - k) / chi;
-  * eutectics: equilibrium compositions of App. B (ternary) or a symmetric
-    binary (0.2, 0.8, liquid 0.5), entropy offsets dS = |c_s - c_l| / 1.2
-    from the solid-liquid slope magnitude 1.2 of App. B;
+  * eutectics with the App. B data (three components): equilibrium
+    compositions c^eq; the coexistence-line slopes m^eq read as dc/dT (their
+    zero entries rule out dT/dc).  The solid-state slopes m^eq_{a-a} move each
+    solid's parabola centre, c0_a(T) = c^eq_a + m^eq_{a-a} (T - T_E) (key mT,
+    liquid 0); the solid-liquid slopes fix the entropy offsets through the
+    liquid composition at a-l coexistence, which moves by m^eq_{a-l} (T - T_E)
+    when dS_a = m^eq_{a-l} . chi^{-1} (c^eq_a - c^eq_l): 0.32 for all three
+    solids (chi = I);
+  * the binary eutectic (no slopes in the paper): a symmetric binary (0.2,
+    0.8, liquid 0.5) with dS = 0.25 and compositions independent of T;
   * drag constant h = 2.757 and interface thickness W0 = eps / dx;
   * noise: sigma = 1e-3 on mu in every cell, drawn from the seed.
 """
@@ -27,6 +34,7 @@ _COMMON = dict(
     noise_sigma=1e-3, seed=1, lam_width=0.0, lam_height=0.0,
     init_center=[0.0, 0.0, 0.0], init_radius=0.0,
     eta=[0.0, 0.0, 0.0],  # shrinkage (rho_a - rho_liq) / rho_liq per phase; the paper's 1.2 / 1.0 gives 0.2
+    mT=[[0.0, 0.0]] * 4,  # d c0_a / dT per phase and solute (0: compositions independent of T)
 )
 
 WORKLOADS = {
@@ -69,7 +77,8 @@ WORKLOADS = {
         _COMMON, dim=3, n=[192, 192, 384], periodic=[1, 1, 0], N=3, nc=2,
         gamma=[[0, 1, 1], [1, 0, 1], [1, 1, 0]], delta=[[0] * 3] * 3,
         c0=[[0.6, 0.2], [0.2, 0.6], [1.0 / 3.0, 1.0 / 3.0]],
-        dS=[0.2484519974999766, 0.2484519974999766, 0.0],
+        mT=[[1.6, 0.0], [0.0, 1.6], [0.0, 0.0]],
+        dS=[0.32, 0.32, 0.0],
         D=[[0.0, 0.0], [0.0, 0.0], [1.0, 1.0]],
         G=5e-5, V=5e-4, y0=30.0, pull_axis=2,
         tau_lb=0.75, gbeta=[5e-6, -2.5e-6], c_ref=[1.0 / 3.0, 1.0 / 3.0],
@@ -77,13 +86,14 @@ WORKLOADS = {
         init="lamellae", lam_width=12.0, lam_height=30.0,
         mu_inf=[0.0, 0.0], steps=10000, precision="fp32"),
     # Case 3: three solids (alpha, beta, gamma) and the liquid, three
-    # components; App. B equilibrium compositions, solid-liquid slopes 1.2;
+    # components; App. B equilibrium compositions and coexistence slopes;
     # the regular alpha-beta-gamma pattern, four periods across (4 lambda x 700)
     "eutectic4": dict(
         _COMMON, dim=2, n=[144, 700], periodic=[1, 0], N=4, nc=2,
         gamma=[[0, 1, 1, 1], [1, 0, 1, 1], [1, 1, 0, 1], [1, 1, 1, 0]], delta=[[0] * 4] * 4,
         c0=[[0.6, 0.2], [0.2, 0.6], [0.2, 0.2], [1.0 / 3.0, 1.0 / 3.0]],
-        dS=[0.24845199749997665, 0.24845199749997665, 0.15713484026367722, 0.0],
+        mT=[[1.6, 0.0], [0.0, 1.6], [-1.6, -1.6], [0.0, 0.0]],
+        dS=[0.32, 0.32, 0.32, 0.0],
         D=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [1.0, 1.0]],
         G=1e-4, V=1e-3, y0=30.0, pull_axis=1,
         tau_lb=0.7, gbeta=[5e-6, -2.5e-6], c_ref=[1.0 / 3.0, 1.0 / 3.0],
@@ -95,7 +105,8 @@ WORKLOADS = {
         _COMMON, dim=3, n=[192, 192, 384], periodic=[1, 1, 0], N=4, nc=2,
         gamma=[[0, 1, 1, 1], [1, 0, 1, 1], [1, 1, 0, 1], [1, 1, 1, 0]], delta=[[0] * 4] * 4,
         c0=[[0.6, 0.2], [0.2, 0.6], [0.2, 0.2], [1.0 / 3.0, 1.0 / 3.0]],
-        dS=[0.24845199749997665, 0.24845199749997665, 0.15713484026367722, 0.0],
+        mT=[[1.6, 0.0], [0.0, 1.6], [-1.6, -1.6], [0.0, 0.0]],
+        dS=[0.32, 0.32, 0.32, 0.0],
         D=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [1.0, 1.0]],
         G=5e-5, V=5e-4, y0=30.0, pull_axis=2,
         tau_lb=0.75, gbeta=[5e-6, -2.5e-6], c_ref=[1.0 / 3.0, 1.0 / 3.0],

@@ -149,16 +149,22 @@ class Step:
             return cf["T_iso"]
         return cf["T_E"] + cf["G"] * (x[cf["pull_axis"]] - cf["y0"] - cf["V"] * n)
 
+    def c0T(self, a, T):
+        """parabola centre of phase a at temperature T: c0 + mT (T - T_E)"""
+        cf = self.cfg
+        mT = np.array(cf.get("mT", [[0.0, 0.0]] * 4)[a][: self.nc], dtype=float)
+        return np.array(cf["c0"][a][: self.nc]) + mT * (T - cf["T_E"])
+
     def psi(self, a, mu, T):
         cf = self.cfg
         chi = np.array(cf["chi"])[: self.nc, : self.nc]
         m = np.array(mu)
-        return -0.5 * m @ chi @ m - m @ np.array(cf["c0"][a][: self.nc]) + cf["dS"][a] * (T - cf["T_E"])
+        return -0.5 * m @ chi @ m - m @ self.c0T(a, T) + cf["dS"][a] * (T - cf["T_E"])
 
-    def C(self, a, mu):
+    def C(self, a, mu, T):
         cf = self.cfg
         chi = np.array(cf["chi"])[: self.nc, : self.nc]
-        return np.array(cf["c0"][a][: self.nc]) + chi @ np.array(mu)
+        return self.c0T(a, T) + chi @ np.array(mu)
 
     # ----- phase field -----
     def faces(self):
@@ -255,11 +261,13 @@ class Step:
         cf, N, nc, d, dx, dt = self.cfg, self.N, self.nc, self.dim, self.cfg["dx"], self.cfg["dt"]
         chi = np.array(cf["chi"])[:nc, :nc]
 
+        n = st["step"]
+
         def quant(x):
             ph = [phin[(b,) + tuple(reversed(x))] for b in range(N)]
             hh = h_funcs(ph)
             mu = [self.at(st["mu"], i, x) for i in range(nc)]
-            cs = sum(hh[b] * self.C(b, mu) for b in range(N))
+            cs = sum(hh[b] * self.C(b, mu, self.temperature(x, n)) for b in range(N))
             M = sum(ph[b] * np.diag(cf["D"][b][:nc]) @ chi for b in range(N))
             return M, cs, np.array(mu)
 
@@ -278,7 +286,9 @@ class Step:
             ph1 = [phin[(b,) + tuple(reversed(x))] for b in range(N)]
             h0, h1 = h_funcs(ph0), h_funcs(ph1)
             mu = [self.at(st["mu"], i, x) for i in range(nc)]
-            Delta = -dt * divJ[x] - sum(self.C(b, mu) * (h1[b] - h0[b]) for b in range(N))
+            T0, T1 = self.temperature(x, n), self.temperature(x, n + 1)
+            Delta = (-dt * divJ[x] - sum(self.C(b, mu, T0) * (h1[b] - h0[b]) for b in range(N))
+                     - sum(h1[b] * (self.C(b, mu, T1) - self.C(b, mu, T0)) for b in range(N)))
             chit = sum(h1) * chi
             m = np.array(mu) + np.linalg.solve(chit, Delta)
             for i in range(nc):
@@ -297,7 +307,7 @@ class Step:
             m = [sum(f[k] * self.c[k][a] for k in range(Q)) for a in range(d)]
             phil = phin[(N - 1,) + tuple(reversed(x))]
             mu = [mun[(i,) + tuple(reversed(x))] for i in range(self.nc)]
-            Cl = self.C(N - 1, mu)
+            Cl = self.C(N - 1, mu, self.temperature(x, st["step"] + 1))
             b = sum(cf["gbeta"][i] * (Cl[i] - cf["c_ref"][i]) for i in range(self.nc))
             FB = [0.0] * d
             FB[cf["grav_axis"]] = -rho * phil * b * cf["grav_sign"]
