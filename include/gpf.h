@@ -107,9 +107,13 @@ typedef struct {
   double dt, eps, tau_pf; /* time step, interface parameter eps, relaxation tau of Eq. (PhfGrand) */
   double gamma[4][4];     /* interface energies gamma_ab, symmetric */
   double delta[4][4];     /* cubic anisotropy strength per pair, symmetric */
-  double chi[2][2];       /* susceptibility, SPD, common to all phases: C^a = c0[a] + chi mu */
+  double chi[2][2];       /* susceptibility, SPD, common to all phases: C^a = c0[a] + mT[a] (T - T_E) + chi mu */
   double c0[4][2];
   double dS[4];           /* grand potential psi^a gets + dS[a] (T - T_E) */
+  double mT[4][2];        /* d c0_a / dT: the parabola centre of phase a is c0[a] + mT[a] (T - T_E),
+                             the equilibrium composition moving along the App. B coexistence line
+                             (slopes read as dc/dT); it makes the dT/dt term of Eq. (conc) act under
+                             the pulled gradient.  All 0: compositions independent of T. */
   double T_E, T_iso;      /* eutectic / equilibrium temperature; temperature when G = 0 */
   double D[4][2];         /* diffusivity per phase and solute (solids 0 in the paper) */
   double G, V, y0;        /* frozen gradient T = T_E + G (x_pull - y0 - V n), V in cells/step */

@@ -135,7 +135,7 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
                                              const R* __restrict__ lf1, const R* __restrict__ lu1,
                                              const R* __restrict__ lmu1, R* __restrict__ lf0,
                                              R* __restrict__ t_phil, R* __restrict__ w,
-                                             R* __restrict__ lmu0, double (&gpart)[NG]) {
+                                             R* __restrict__ lmu0, R tshift1, double (&gpart)[NG]) {
   using L = Lat<Q>;
   {
     R f[TAPE ? 1 : L::Q], ob[L::Q];
@@ -179,10 +179,13 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
       }
     }
     const R rho = p.rho0 + dr;
+    // the liquid's composition at the step's new temperature T^{n+1}
+    const int pos[3] = {x, y, z};
+    const R td1 = tdev_at(p, pos[p.pull_axis], tshift1);
     R Cl[NC], bsum = R(0);
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      Cl[i] = p.c0s[N - 1][i];
+      Cl[i] = p.c0s[N - 1][i] + p.mT[N - 1][i] * td1;
 #pragma unroll
       for (int k = 0; k < NC; ++k) Cl[i] += p.chi[i][k] * mu[k];
       bsum += p.gbeta[i] * (Cl[i] - p.c_ref[i]);
@@ -320,13 +323,13 @@ __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
           const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
           const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
-          R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
+          R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, R tshift1, double* __restrict__ part) {
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
   int64_t P;
   int x, y, z;
   if (adj_cell(p.n, p.sy, p.sz, P, x, y, z))
     adj_lbm_cell<D, Q, N, NC, R, TAPE>(p, P, x, y, z, fst, dr_t, u1, phi1, mu1, lf1, lu1, lmu1, lf0, t_phil, w,
-                                       lmu0, gpart);
+                                       lmu0, tshift1, gpart);
   block_partials(gpart, part);
 }
 
@@ -335,7 +338,7 @@ k_adj_lbm(KP<R> p, const R* __restrict__ fst, const R* __restrict__ dr_t, const 
 // projection and local phase-field terms of the same cell
 // ---------------------------------------------------------------------------
 template <int N, int NC, class R>
-__device__ __forceinline__ void mu_quant(const KP<R>& p, const R (&ph)[N], const R (&m)[NC],
+__device__ __forceinline__ void mu_quant(const KP<R>& p, const R (&ph)[N], const R (&m)[NC], R td,
                                          R (&M)[NC][NC], R (&cs)[NC]) {
   R h[N];
   interp_h<N, R>(ph, h);
@@ -349,7 +352,7 @@ __device__ __forceinline__ void mu_quant(const KP<R>& p, const R (&ph)[N], const
   for (int b = 0; b < N; ++b)
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      R C = p.c0s[b][i];
+      R C = p.c0s[b][i] + p.mT[b][i] * td;
 #pragma unroll
       for (int k = 0; k < NC; ++k) C += p.chi[i][k] * m[k];
       cs[i] += h[b] * C;
@@ -362,12 +365,14 @@ template <int D, int N, int NC, class R>
 __device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, int y, int z,
                                             const R* __restrict__ phi0, const R* __restrict__ phi1,
                                             const R* __restrict__ mu0, const R* __restrict__ mu1,
-                                            const R* __restrict__ u0, const R* __restrict__ w,
+                                            const R* __restrict__ u0, const R* __restrict__ w, R tshift,
                                             R (&mub_o)[NC], R (&Ub_o)[D], R (&p1b_o)[N], R (&p0b_o)[N],
                                             double (&gpart)[NG]) {
   {
     const int pos[3] = {x, y, z};
     const int64_t stride[3] = {1, p.sy, p.sz};
+    const int pa = p.pull_axis;
+    const R tdP = tdev_at(p, pos[pa], tshift);
     R php[N], mp[NC], wp[NC], MP[NC][NC], cP[NC];
 #pragma unroll
     for (int b = 0; b < N; ++b) php[b] = phi1[b * p.cells + P];
@@ -376,7 +381,7 @@ __device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, in
       mp[i] = mu0[i * p.cells + P];
       wp[i] = w[i * p.cells + P];
     }
-    mu_quant<N, NC, R>(p, php, mp, MP, cP);
+    mu_quant<N, NC, R>(p, php, mp, tdP, MP, cP);
     R mub[NC], Mb[NC][NC], cb[NC], Ub[D];
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
@@ -406,7 +411,7 @@ __device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, in
           mq[i] = mu0[i * p.cells + Qj];
           wq[i] = w[i * p.cells + Qj];
         }
-        mu_quant<N, NC, R>(p, phq, mq, MQ, cQ);
+        mu_quant<N, NC, R>(p, phq, mq, a == pa ? tdev_at(p, q, tshift) : tdP, MQ, cQ);
         const R uaQ = u0[a * p.cells + Qj];
         // the face with left cell L and right cell R = L + e_a
         const R sgn = (s > 0) ? R(1) : R(-1);  // +1: this cell is L
@@ -449,16 +454,18 @@ __device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, in
     R h1b[N], h0b[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      R wC = R(0), cC = R(0);
+      R wC = R(0), cC = R(0), wT = R(0);
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
-        R C = p.c0s[b][i];
+        R C = p.c0s[b][i] + p.mT[b][i] * tdP;
 #pragma unroll
         for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mp[k];
         wC += wp[i] * C;
         cC += cb[i] * C;
+        wT += wp[i] * p.mT[b][i];
       }
-      h1b[b] = -wC - wchidm + cC;
+      // the dT/dt term -h1_b mT[b] (T^{n+1} - T^n) of the update
+      h1b[b] = -wC - wchidm + cC - wT * p.dtdev;
       h0b[b] = wC;
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
@@ -529,7 +536,7 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
   int x, y, z;
   if (adj_cell(p.n, p.sy, p.sz, P, x, y, z)) {
     R mubf[NC], Ubf[D], p1bf[N], p0bf[N];
-    mu_adj_cell<D, N, NC, R>(p, P, x, y, z, phi0, phi1, mu0, mu1, u0, w, mubf, Ubf, p1bf, p0bf, gpart);
+    mu_adj_cell<D, N, NC, R>(p, P, x, y, z, phi0, phi1, mu0, mu1, u0, w, tshift, mubf, Ubf, p1bf, p0bf, gpart);
 #pragma unroll
     for (int a = 0; a < D; ++a) lu0[a * p.cells + P] = Ubf[a];
     R v[N][3][3][3];
@@ -606,8 +613,8 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           R chimu = R(0);
 #pragma unroll
           for (int j = 0; j < NC; ++j) chimu += p.chi[i][j] * m[j];
-          r += -R(0.5) * m[i] * chimu - m[i] * p.c0[b][i];
-          C[b][i] = p.c0[b][i] + chimu;
+          r += -R(0.5) * m[i] * chimu - m[i] * (p.c0[b][i] + p.mT[b][i] * tdev);
+          C[b][i] = p.c0[b][i] + p.mT[b][i] * tdev + chimu;
         }
         ps[b] = r + p.dS[b] * tdev;
       }
@@ -1105,7 +1112,8 @@ k_adj_phi2_lbm(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__
                const uint8_t* __restrict__ rowflag, uint8_t* __restrict__ rowclear, const R* __restrict__ fst, const R* __restrict__ dr_t, const R* __restrict__ u1,
                const R* __restrict__ phi1, const R* __restrict__ mu1, const R* __restrict__ lf1,
                const R* __restrict__ lu1, const R* __restrict__ lmu1, R* __restrict__ lf0,
-               R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, double* __restrict__ part) {
+               R* __restrict__ t_phil, R* __restrict__ w, R* __restrict__ lmu0, R tshift1,
+               double* __restrict__ part) {
   const unsigned nb = gridDim.x / 2u;
   int64_t P;
   int xc[3];
@@ -1117,7 +1125,7 @@ k_adj_phi2_lbm(KP<R> p, const uint8_t* __restrict__ rflag, const R* __restrict__
     double gpart[NG] = {0, 0, 0, 0, 0, 0};
     if (adj_cell(p.n, p.sy, p.sz, P, xc[0], xc[1], xc[2], blk))
       adj_lbm_cell<D, Q, N, NC, R, TAPE>(p, P, xc[0], xc[1], xc[2], fst, dr_t, u1, phi1, mu1, lf1, lu1, lmu1,
-                                         lf0, t_phil, w, lmu0, gpart);
+                                         lf0, t_phil, w, lmu0, tshift1, gpart);
     block_partials(gpart, part, blk);
   }
 }

@@ -162,7 +162,7 @@ __device__ __forceinline__ void pf_rhs(const KP<R>& p, const R (&v)[N][3][3][3],
       }
     }
 
-  // grand potentials psi^b(mu, T) = -1/2 mu.chi.mu - mu.c0[b] + dS[b] (T - T_E)
+  // grand potentials psi^b(mu, T) = -1/2 mu.chi.mu - mu.(c0[b] + mT[b] (T - T_E)) + dS[b] (T - T_E)
   R m[NC];
 #pragma unroll
   for (int i = 0; i < NC; ++i) m[i] = p.mu_ref[i] + mu[i * p.cells + P];
@@ -176,7 +176,7 @@ __device__ __forceinline__ void pf_rhs(const KP<R>& p, const R (&v)[N][3][3][3],
       R chimu = R(0);
 #pragma unroll
       for (int j = 0; j < NC; ++j) chimu += p.chi[i][j] * m[j];
-      r += -R(0.5) * m[i] * chimu - m[i] * p.c0[b][i];
+      r += -R(0.5) * m[i] * chimu - m[i] * (p.c0[b][i] + p.mT[b][i] * tdev);
     }
     ps[b] = r + p.dS[b] * tdev;
   }
@@ -232,8 +232,14 @@ __device__ __forceinline__ bool phi_from_stencil(const KP<R>& p, const R (&v)[N]
 // ---------------------------------------------------------------------------
 // SH: the shrinkage force is on (a separate instance keeps the registers of
 // the common case unchanged)
+// T - T_E of a cell at pull-axis coordinate c, step shift ts
+template <class R>
+__device__ __forceinline__ R tdev_at(const KP<R>& p, int c, R ts) {
+  return (p.G != R(0)) ? p.G * (R(c) - ts) : p.tdev_iso;
+}
+
 template <int D, int Q, int N, int NC, class R, bool SH>
-__device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
+__device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, R ts0,
                                            const R (&ph1n)[2 * D + 1][N],
                                            const R (&mun)[2 * D + 1][NC], const R (&uc)[D],
                                            const R (&un)[D][2], const R (&ph0)[N],
@@ -243,9 +249,16 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
   using L = Lat<Q>;
   const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
   const int pos[3] = {x, y, z};
+  // T^n - T_E at the cell and at its pull-axis neighbours (slots of ph1n)
+  const int pa = p.pull_axis;
+  auto tdev_slot = [&](int slot) -> R {
+    if (slot == 0 || (slot - 1) / 2 != pa) return tdev_at(p, pos[pa], ts0);
+    return tdev_at(p, nb_field(pos[pa], ((slot - 1) & 1) ? 1 : -1, p.n[pa], p.per[pa]), ts0);
+  };
 
-  // per-cell quantities at phi^{n+1}: c* = sum h C(mu^n), M = sum phi D chi
+  // per-cell quantities at phi^{n+1}: c* = sum h C(mu^n, T^n), M = sum phi D chi
   auto quant = [&](int slot, R (&M)[NC][NC], R (&cs)[NC]) {
+    const R td = tdev_slot(slot);
     R ph[N], h[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) ph[b] = ph1n[slot][b];
@@ -260,7 +273,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
     for (int b = 0; b < N; ++b) {
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
-        R C = p.c0s[b][i];
+        R C = p.c0s[b][i] + p.mT[b][i] * td;
 #pragma unroll
         for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mun[slot][k];
         cs[i] += h[b] * C;
@@ -307,16 +320,21 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
   R Dl[NC];
 #pragma unroll
   for (int i = 0; i < NC; ++i) Dl[i] = -p.dt * divJ[i];
+  // dh/dt source with C at T^n, and the dT/dt term of Eq. (conc) over the
+  // step, -sum_b h_b^{n+1} (C^b(mu^n, T^{n+1}) - C^b(mu^n, T^n)) = -sum_b
+  // h_b^{n+1} mT[b] (T^{n+1} - T^n)
+  const R td0 = tdev_slot(0);
   R sh = R(0);
 #pragma unroll
   for (int b = 0; b < N; ++b) {
     sh += h1[b];
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      R C = p.c0s[b][i];
+      R C = p.c0s[b][i] + p.mT[b][i] * td0;
 #pragma unroll
       for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mun[0][k];
       Dl[i] -= C * (h1[b] - h0[b]);
+      Dl[i] -= h1[b] * (p.mT[b][i] * p.dtdev);
     }
   }
   R mn[NC];
@@ -353,7 +371,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z,
   R bsum = R(0);
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
-    R Cl = p.c0s[N - 1][i];
+    R Cl = p.c0s[N - 1][i] + p.mT[N - 1][i] * (td0 + p.dtdev);  // the liquid at T^{n+1}
 #pragma unroll
     for (int k = 0; k < NC; ++k) Cl += p.chi[i][k] * mn[k];
     bsum += p.gbeta[i] * (Cl - p.c_ref[i]);
@@ -576,7 +594,7 @@ __global__ void __launch_bounds__(TX * TY)
 k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
           R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout, R* __restrict__ dr_out,
-          int tiles_x, int tiles_y, int zc) {
+          R tshift, int tiles_x, int tiles_y, int zc) {
   static_assert(TX >= 2 && TY >= 2, "edge threads own one row and one column halo cell at most");
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
   constexpr int NV = N + NC + 2;  // phi^{n+1}, mu^n, U_x, U_y per tile cell
@@ -706,7 +724,8 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
         un[D - 1][0] = cuz[0];
         un[D - 1][1] = cuz[2];
       }
-      mulbm_core<D, Q, N, NC, R, SH>(p, xq, yq, z, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout, dr_out);
+      mulbm_core<D, Q, N, NC, R, SH>(p, xq, yq, z, tshift, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout,
+                                     dr_out);
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
@@ -869,10 +888,12 @@ __global__ void k_derived(KP<R> p, int which, const R* __restrict__ phi, const R
     for (int b = 0; b < N; ++b) ph[b] = (double)phi[b * p.cells + P];
     for (int i = 0; i < NC; ++i) m[i] = (double)mu[i * p.cells + P];
     interp_h<N, double>(ph, h);
+    const int pos[3] = {x, y, z};
+    const double td = (p.G != R(0)) ? (double)p.G * ((double)pos[p.pull_axis] - tshift_d) : (double)p.tdev_iso;
     for (int i = 0; i < NC; ++i) {
       double c = 0.0;
       for (int b = 0; b < N; ++b) {
-        double C = p.c0s_d[b][i];
+        double C = p.c0s_d[b][i] + (double)p.mT[b][i] * td;
         for (int k = 0; k < NC; ++k) C += (double)p.chi[i][k] * m[k];
         c += h[b] * C;
       }
@@ -902,7 +923,8 @@ constexpr int RED_BLOCK = 256;
 template <int D, int Q, int N, int NC, class R>
 __global__ void __launch_bounds__(RED_BLOCK)
 k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ mu,
-          const R* __restrict__ f, const double* __restrict__ target, double* __restrict__ partial) {
+          const R* __restrict__ f, const double* __restrict__ target, double tshift_d,
+          double* __restrict__ partial) {
   using L = Lat<Q>;
   __shared__ double sh[NC][RED_BLOCK];
   const int t = threadIdx.x;
@@ -915,10 +937,12 @@ k_partial(KP<R> p, int which, const R* __restrict__ phi, const R* __restrict__ m
       for (int b = 0; b < N; ++b) ph[b] = (double)phi[b * p.cells + P];
       for (int i = 0; i < NC; ++i) m[i] = (double)mu[i * p.cells + P];
       interp_h<N, double>(ph, h);
+      const int pos[3] = {(int)(P % p.n[0]), (int)((P / p.sy) % p.n[1]), (int)(P / p.sz)};
+      const double td = (p.G != R(0)) ? (double)p.G * ((double)pos[p.pull_axis] - tshift_d) : (double)p.tdev_iso;
       for (int i = 0; i < NC; ++i) {
         double c = 0.0;
         for (int b = 0; b < N; ++b) {
-          double C = p.c0s_d[b][i];
+          double C = p.c0s_d[b][i] + (double)p.mT[b][i] * td;
           for (int k = 0; k < NC; ++k) C += (double)p.chi[i][k] * m[k];
           c += h[b] * C;
         }

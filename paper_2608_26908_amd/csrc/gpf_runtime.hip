@@ -189,6 +189,9 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
     }
   k.G = (R)p.G;
   k.tdev_iso = (R)(p.T_iso - p.T_E);
+  for (int a = 0; a < 4; ++a)
+    for (int i = 0; i < 2; ++i) k.mT[a][i] = (a < c->N && i < c->nc) ? (R)p.mT[a][i] : R(0);
+  k.dtdev = (R)(p.G != 0.0 ? -p.G * p.V : 0.0);
   k.T_E = (R)p.T_E;
   k.tau_lb = (R)p.tau_lb;
   k.rho0 = (R)p.rho0;
@@ -336,11 +339,11 @@ struct Impl {
     if (ev) (void)hipEventRecord(ev[1], st);
     if (k.shrink)
       hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, true>), grid(kZChunkMu), block, 0, st, k,
-                         in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y,
+                         in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, ts, tiles_x, tiles_y,
                          kZChunkMu);
     else
       hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, false>), grid(kZChunkMu), block, 0, st, k,
-                         in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, tiles_x, tiles_y,
+                         in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, ts, tiles_x, tiles_y,
                          kZChunkMu);
     if (ev) (void)hipEventRecord(ev[2], st);
   }
@@ -550,7 +553,7 @@ struct Impl {
     const int nblk = reduce_blocks(c);
     const int ncomp = which == GPF_SUM_SOLUTE ? NC : 1;
     hipLaunchKernelGGL((gpf::k_partial<D, Q, N, NC, R>), dim3(nblk), dim3(gpf::RED_BLOCK), 0, c->stream, k,
-                       which, P(c->phi[s]), P(c->mu[s]), P(c->f[s]), c->target, partial);
+                       which, P(c->phi[s]), P(c->mu[s]), P(c->f[s]), c->target, tshift(c, c->step), partial);
     hipLaunchKernelGGL(gpf::k_final_sum, dim3(1), dim3(gpf::RED_BLOCK), 0, c->stream, partial, nblk, ncomp,
                        dev_out);
     HIP_OR_FAIL(c, hipGetLastError());
@@ -639,16 +642,19 @@ struct Impl {
   static uint8_t* rowflags(gpf_ctx* c, int64_t n) {
     return static_cast<uint8_t*>(c->t_rowflag.ptr) + (n & 1) * c->n[1] * c->n[2];
   }
-  static void adj_lbm(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, StateBuf& li, StateBuf& lo) {
+  // LBM reverse of step n (X^n -> X^{n+1}); its forces used T^{n+1}
+  static void adj_lbm(gpf_ctx* c, const gpf::KP<R>& k, int64_t n, const SP& x0, const SP& x1, StateBuf& li,
+                      StateBuf& lo) {
     const AdjLaunch a = adj_launch(c);
+    const R ts1 = (R)tshift(c, n + 1);
     if (x1.dr)
       hipLaunchKernelGGL((gpf::k_adj_lbm<D, Q, N, NC, R, true>), a.g, a.b, 0, c->stream, k, x0.f, x1.dr, x1.u,
                          x1.phi, x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu),
-                         a.part);
+                         ts1, a.part);
     else
       hipLaunchKernelGGL((gpf::k_adj_lbm<D, Q, N, NC, R, false>), a.g, a.b, 0, c->stream, k, x0.f, x1.dr, x1.u,
                          x1.phi, x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu),
-                         a.part);
+                         ts1, a.part);
   }
   static void adj_muphi_vjp(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, int64_t n,
                             StateBuf& li, StateBuf& lo) {
@@ -678,13 +684,13 @@ struct Impl {
                          a.rflag,
                          P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), rowflags(c, n), rowflags(c, n + 1), x0.f,
                          x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
-                         P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), a.part);
+                         P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), (R)tshift(c, n), a.part);
     else
       hipLaunchKernelGGL((gpf::k_adj_phi2_lbm<D, Q, N, NC, R, false>), dim3(2 * a.g.x), a.b, 0, c->stream, k,
                          a.rflag,
                          P(c->t_fbuf), a.fflag, P(c->t_cbuf), P(lo.phi), rowflags(c, n), rowflags(c, n + 1), x0.f,
                          x1.dr, x1.u, x1.phi, x1.mu, P(lo.f),
-                         P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), a.part);
+                         P(lo.u), P(lo.mu), P(li.f), P(c->t_phil), P(c->t_w), P(li.mu), (R)tshift(c, n), a.part);
   }
 
   // seed: dL/dphi at the current (final) state, FP64, N * cells values, in
@@ -818,7 +824,7 @@ struct Impl {
     // alone) cost more than the boundary.
     const bool fuse = small_grid(c);
     for (int64_t j = 0; j < seg_len(nseg - 1) - 1; ++j) recompute_step(0, nseg - 1, j, c->stream);
-    adj_lbm(c, k, state(total - 1), state(total), *li, *lo);
+    adj_lbm(c, k, c->rec_start + total - 1, state(total - 1), state(total), *li, *lo);
     int64_t nrec = 0, jr = 0;
     for (int64_t m = total - 1; m >= 0; --m) {
       const int64_t sg = m / K, j = m % K;
@@ -852,7 +858,7 @@ struct Impl {
           adj_phi2_lbm(c, k, c->rec_start + m, state(m - 1), state(m), *lo, *li);
         } else {
           adj_phi2(c, k, c->rec_start + m, *lo);
-          adj_lbm(c, k, state(m - 1), state(m), *lo, *li);
+          adj_lbm(c, k, c->rec_start + m - 1, state(m - 1), state(m), *lo, *li);
         }
       } else {
         adj_phi2(c, k, c->rec_start + m, *lo);

@@ -45,7 +45,8 @@ class ParamsC(ctypes.Structure):
         ("dt", ctypes.c_double), ("eps", ctypes.c_double), ("tau_pf", ctypes.c_double),
         ("gamma", (ctypes.c_double * 4) * 4), ("delta", (ctypes.c_double * 4) * 4),
         ("chi", (ctypes.c_double * 2) * 2), ("c0", (ctypes.c_double * 2) * 4),
-        ("dS", ctypes.c_double * 4), ("T_E", ctypes.c_double), ("T_iso", ctypes.c_double),
+        ("dS", ctypes.c_double * 4), ("mT", (ctypes.c_double * 2) * 4),
+        ("T_E", ctypes.c_double), ("T_iso", ctypes.c_double),
         ("D", (ctypes.c_double * 2) * 4),
         ("G", ctypes.c_double), ("V", ctypes.c_double), ("y0", ctypes.c_double),
         ("pull_axis", ctypes.c_int32),
@@ -143,6 +144,7 @@ def make_params(cfg, precision):
     p.init_kind = {"seed": 0, "lamellae": 1, "liquid": 2}[cfg.get("init", "seed")]
     for name in ("gamma", "delta", "chi", "c0", "dS", "D", "gbeta", "c_ref", "mu_inf"):
         _fill(getattr(p, name), cfg[name])
+    _fill(p.mT, cfg.get("mT", [[0.0, 0.0]] * 4))
     _fill(p.init_center, cfg.get("init_center", [0.0, 0.0, 0.0]))
     _fill(p.eta, cfg.get("eta", [0.0, 0.0, 0.0]))
     p.health_every = int(cfg.get("health_every", 0))

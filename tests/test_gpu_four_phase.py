@@ -125,3 +125,71 @@ def test_parameter_gradients_match_complex_step_fp64(oracle):
     for name, gv in zip(names, grads):
         L, ref = o.loss_grad_cs(steps, target, name)
         assert gv == pytest.approx(ref, rel=1e-8, abs=1e-14 * abs(L)), (name, gv, ref)
+
+
+# ---------------- temperature-dependent compositions (App. B slopes) --------------
+
+STRONG = dict(G=2e-3, V=0.05)  # T falls by 1e-4 per step: the dT/dt term of Eq. (conc) dominates
+
+
+@pytest.mark.parametrize("name,n", [("eutectic4", [36, 40]), ("eutectic3d", [24, 20, 24])])
+def test_pulled_compositions_fp64(oracle, name, n):
+    """Under a strongly pulled gradient the solids' equilibrium compositions
+    move by 1.6e-4 per step: FP64 parity with the oracle after 200 steps and
+    the solute total conserved to 1e-12 relative by the GPU's own FP64 sums."""
+    from paper_2608_26908_amd.gpf import Sim
+    h = 12.0 if len(n) == 2 else 8.0
+    cfg = scaled(name, n, y0=h, lam_height=h, **STRONG)
+    g, o = Sim(cfg, precision="fp64"), oracle.OracleSim(cfg)
+    s0 = g.reduce("solute")
+    g.step(200)
+    o.step(200)
+    _cmp(g, o)
+    assert rel_err(g.read("c"), o.get("c")) <= TOL64
+    s1 = g.reduce("solute")
+    assert np.abs(s1 - s0).max() <= 1e-12 * np.abs(s0).max()
+    g.close()
+
+
+def test_pulled_compositions_fp32(oracle):
+    """The same in FP32 storage and arithmetic (the term formed from the
+    FP64 step temperature change on the host): within the FP32 tolerance of
+    the FP64 oracle after 100 steps."""
+    from paper_2608_26908_amd.gpf import Sim
+    cfg = scaled("eutectic4", [72, 64], y0=12.0, lam_height=12.0, gbeta=[2e-3, -1e-3], **STRONG)
+    g, o = Sim(cfg, precision="fp32"), oracle.OracleSim(cfg)
+    g.step(100)
+    o.step(100)
+    dphi = np.abs(g.read("phi") - o.get("phi")).max()
+    ug, uo = g.read("u"), o.get("u")
+    rl2 = np.sqrt(((ug - uo) ** 2).sum() / (uo ** 2).sum())
+    assert dphi <= 1e-5, dphi
+    assert rl2 <= 1e-4, rl2
+    assert rel_err(g.read("mu"), o.get("mu")) <= 1e-5
+    g.close()
+
+
+@pytest.mark.parametrize("kind", ["quaternary2d", "ternary3d_nc2"])
+def test_adjoint_dot_product_pulled_compositions(oracle, kind):
+    """The adjoint includes the dT/dt term and the compositions at T^n and
+    T^{n+1}: dot-product identity against the oracle's complex-step tangent
+    under the strongly pulled gradient, for phi, mu, U and f perturbations."""
+    from inputs import busy_config
+    n = [30, 26] if "2d" in kind else [14, 12, 13]
+    cfg = busy_config(kind, n, **STRONG)
+    st = random_state(cfg, 17)
+    steps, K = 6, 3
+    g = gpu_from(cfg, st, "fp64")
+    g.record(K)
+    g.step(steps)
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal((cfg["N"],) + g.shape)
+    g.adjoint(w, [])
+    o = oracle_from(cfg, st)
+    for field in ("phi", "mu", "u", "f"):
+        lam = g.adjoint_state(field)
+        v = rng.standard_normal(lam.shape)
+        t = o.tangent_cs(steps, field, v, "phi")
+        lhs, rhs = float((w * t).sum()), float((lam * v).sum())
+        assert abs(lhs - rhs) <= 1e-9 * max(abs(lhs), abs(rhs), 1e-30), (field, lhs, rhs)
+    g.close()
