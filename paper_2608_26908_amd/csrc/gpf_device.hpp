@@ -97,6 +97,7 @@ template <class R> struct KP {
   R G, tdev_iso, T_E;     // T - T_E = G (x_pull - shift) if G != 0, else tdev_iso
   R mT[4][2];             // d c0_a / dT: C^a = c0s[a] + mT[a] (T - T_E) + chi (mu - mu_ref)
   R dtdev;                // T^{n+1} - T^n of one step, -G V (formed in FP64 on the host)
+  int tdep;               // some mT != 0 (the compositions depend on T)
   R tau_lb, rho0, gbeta[2], c_ref[2], grav_sign, kappa, lid_u;
   R eta[4];               // shrinkage (rho_a - rho_liq) / rho_liq per phase
   int shrink;             // some eta != 0

@@ -238,7 +238,9 @@ __device__ __forceinline__ R tdev_at(const KP<R>& p, int c, R ts) {
   return (p.G != R(0)) ? p.G * (R(c) - ts) : p.tdev_iso;
 }
 
-template <int D, int Q, int N, int NC, class R, bool SH>
+// MT: the equilibrium compositions depend on T (some mT != 0); a separate
+// instance keeps the registers of the common case
+template <int D, int Q, int N, int NC, class R, bool SH, bool MT>
 __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, R ts0,
                                            const R (&ph1n)[2 * D + 1][N],
                                            const R (&mun)[2 * D + 1][NC], const R (&uc)[D],
@@ -252,6 +254,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
   // T^n - T_E at the cell and at its pull-axis neighbours (slots of ph1n)
   const int pa = p.pull_axis;
   auto tdev_slot = [&](int slot) -> R {
+    if constexpr (!MT) return R(0);
     if (slot == 0 || (slot - 1) / 2 != pa) return tdev_at(p, pos[pa], ts0);
     return tdev_at(p, nb_field(pos[pa], ((slot - 1) & 1) ? 1 : -1, p.n[pa], p.per[pa]), ts0);
   };
@@ -273,7 +276,8 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
     for (int b = 0; b < N; ++b) {
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
-        R C = p.c0s[b][i] + p.mT[b][i] * td;
+        R C = p.c0s[b][i];
+        if constexpr (MT) C += p.mT[b][i] * td;
 #pragma unroll
         for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mun[slot][k];
         cs[i] += h[b] * C;
@@ -330,11 +334,12 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
     sh += h1[b];
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      R C = p.c0s[b][i] + p.mT[b][i] * td0;
+      R C = p.c0s[b][i];
+      if constexpr (MT) C += p.mT[b][i] * td0;
 #pragma unroll
       for (int k = 0; k < NC; ++k) C += p.chi[i][k] * mun[0][k];
       Dl[i] -= C * (h1[b] - h0[b]);
-      Dl[i] -= h1[b] * (p.mT[b][i] * p.dtdev);
+      if constexpr (MT) Dl[i] -= h1[b] * (p.mT[b][i] * p.dtdev);
     }
   }
   R mn[NC];
@@ -371,7 +376,8 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
   R bsum = R(0);
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
-    R Cl = p.c0s[N - 1][i] + p.mT[N - 1][i] * (td0 + p.dtdev);  // the liquid at T^{n+1}
+    R Cl = p.c0s[N - 1][i];
+    if constexpr (MT) Cl += p.mT[N - 1][i] * (td0 + p.dtdev);  // the liquid at T^{n+1}
 #pragma unroll
     for (int k = 0; k < NC; ++k) Cl += p.chi[i][k] * mn[k];
     bsum += p.gbeta[i] * (Cl - p.c_ref[i]);
@@ -589,7 +595,7 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
 // barrier per plane.  Threads past the grid's edge hold the wrapped (periodic)
 // or clamped (wall) column, which only serves as a neighbour.
 // ---------------------------------------------------------------------------
-template <int D, int Q, int N, int NC, class R, int TX, int TY, bool SH>
+template <int D, int Q, int N, int NC, class R, int TX, int TY, bool SH, bool MT>
 __global__ void __launch_bounds__(TX * TY)
 k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
@@ -724,8 +730,8 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
         un[D - 1][0] = cuz[0];
         un[D - 1][1] = cuz[2];
       }
-      mulbm_core<D, Q, N, NC, R, SH>(p, xq, yq, z, tshift, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout,
-                                     dr_out);
+      mulbm_core<D, Q, N, NC, R, SH, MT>(p, xq, yq, z, tshift, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout,
+                                         dr_out);
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {

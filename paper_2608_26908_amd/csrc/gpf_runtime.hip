@@ -189,8 +189,12 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
     }
   k.G = (R)p.G;
   k.tdev_iso = (R)(p.T_iso - p.T_E);
+  k.tdep = 0;
   for (int a = 0; a < 4; ++a)
-    for (int i = 0; i < 2; ++i) k.mT[a][i] = (a < c->N && i < c->nc) ? (R)p.mT[a][i] : R(0);
+    for (int i = 0; i < 2; ++i) {
+      k.mT[a][i] = (a < c->N && i < c->nc) ? (R)p.mT[a][i] : R(0);
+      if (k.mT[a][i] != R(0)) k.tdep = 1;
+    }
   k.dtdev = (R)(p.G != 0.0 ? -p.G * p.V : 0.0);
   k.T_E = (R)p.T_E;
   k.tau_lb = (R)p.tau_lb;
@@ -337,14 +341,20 @@ struct Impl {
     hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid(kZChunkPhi), block, 0, st, k, in.phi,
                        in.mu, out.phi, bulk_in, bulk_out, ts, tiles_x, tiles_y, kZChunkPhi);
     if (ev) (void)hipEventRecord(ev[1], st);
-    if (k.shrink)
-      hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, true>), grid(kZChunkMu), block, 0, st, k,
-                         in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, ts, tiles_x, tiles_y,
-                         kZChunkMu);
-    else
-      hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, false>), grid(kZChunkMu), block, 0, st, k,
-                         in.phi, out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, ts, tiles_x, tiles_y,
-                         kZChunkMu);
+#define GPF_MULBM(SH, MT)                                                                                     \
+  hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, SH, MT>), grid(kZChunkMu), block, 0, st, k, in.phi, \
+                     out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, ts, tiles_x, tiles_y, kZChunkMu)
+    if (k.shrink) {
+      if (k.tdep)
+        GPF_MULBM(true, true);
+      else
+        GPF_MULBM(true, false);
+    } else if (k.tdep) {
+      GPF_MULBM(false, true);
+    } else {
+      GPF_MULBM(false, false);
+    }
+#undef GPF_MULBM
     if (ev) (void)hipEventRecord(ev[2], st);
   }
 
