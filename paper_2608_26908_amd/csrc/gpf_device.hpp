@@ -99,6 +99,9 @@ template <class R> struct KP {
   R dtdev;                // T^{n+1} - T^n of one step, -G V (formed in FP64 on the host)
   int tdep;               // some mT != 0 (the compositions depend on T)
   R tau_lb, rho0, gbeta[2], c_ref[2], grav_sign, kappa, lid_u;
+  // formed in FP64 on the host: 1 / tau_lb, the Guo prefactor 1 - 1 / (2 tau_lb),
+  // 1 / dx and the lattice-to-phase-field velocity factor dx / dt
+  R omega, guo, idx, conv;
   R eta[4];               // shrinkage (rho_a - rho_liq) / rho_liq per phase
   int shrink;             // some eta != 0
   R qmin2;                // |q|^2 below which the anisotropy direction is undefined

@@ -42,8 +42,93 @@ __device__ __forceinline__ R pull_f(const KP<R>& p, const R* __restrict__ fin, i
     return __builtin_nontemporal_load(&fin[k * p.cells + (int64_t)src[2] * p.sz + (int64_t)src[1] * p.sy + src[0]]);
   R val = fin[Lat<Q>::opp(k) * p.cells + P];
   if (L::c(k, 1) < 0 && !p.per[1] && y - L::c(k, 1) >= p.n[1])
-    val += R(6) * p.w[k] * p.rho0 * R(L::c(k, 0)) * p.lid_u;
+    val += R(6 * L::w(k)) * p.rho0 * R(L::c(k, 0)) * p.lid_u;
   return val;
+}
+
+// Element u + l of a buffer, u wave-uniform and l a lane's own non-negative
+// offset: the uniform part is formed in scalar registers and the access is a
+// global load or store with a scalar base and a 32-bit lane offset.
+template <class T>
+__device__ __forceinline__ T* lane_at(T* base, int64_t u, int l) {
+  using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<C*>(base + u) + (uint32_t)l * (uint32_t)sizeof(T));
+}
+
+// Source columns of the pulls of one lane along x, fixed for a z-marching
+// thread: xs[1 - c_x] is the column of the cell P - c_k (wrapped on a
+// periodic axis, clamped at a wall) and xw[1 - c_x] says it lies behind a wall.
+struct PullX {
+  int xs[3];
+  bool xw[3];
+};
+__device__ __forceinline__ PullX pull_x(int x, int n0, int per0) {
+  PullX q;
+  q.xs[1] = x;
+  q.xw[1] = false;
+  q.xw[0] = !per0 && x - 1 < 0;
+  q.xw[2] = !per0 && x + 1 >= n0;
+  q.xs[0] = (x - 1 < 0) ? (per0 ? x - 1 + n0 : 0) : x - 1;
+  q.xs[2] = (x + 1 >= n0) ? (per0 ? x + 1 - n0 : n0 - 1) : x + 1;
+  return q;
+}
+
+// The populations f^n of the cell (x, y, z) for a wave whose lanes share the
+// row y and plane z (what pull_f does cell by cell): the source row and plane
+// of population k, and with them a wall between source and cell along y or z,
+// are the same on every lane, so they are decided with scalar arithmetic and
+// only the x walls of the grid's first and last column differ between lanes.
+template <int D, int Q, class R>
+__device__ __forceinline__ void pull_row(const KP<R>& p, const R* __restrict__ fin, int x, int y, int z,
+                                         const PullX& px, R (&f)[Q]) {
+  using L = Lat<Q>;
+  const int64_t own = (int64_t)z * p.sz + (int64_t)y * p.sy;
+  // source row and plane of population k; false when behind a y or z wall
+  auto src = [&](int k, int64_t& row) -> bool {
+    int ys = y - L::c(k, 1), zs = (D == 3) ? z - L::c(k, 2) : z;
+    bool in = true;
+    if (ys < 0 || ys >= p.n[1]) {
+      if (p.per[1])
+        ys += (ys < 0) ? p.n[1] : -p.n[1];
+      else
+        in = false;
+    }
+    if (D == 3 && (zs < 0 || zs >= p.n[2])) {
+      if (p.per[2])
+        zs += (zs < 0) ? p.n[2] : -p.n[2];
+      else
+        in = false;
+    }
+    row = (int64_t)zs * p.sz + (int64_t)ys * p.sy;
+    return in;
+  };
+  // reflected population at the cell itself (half-way bounce-back), plus the
+  // moving-lid term where the source lies above the upper y wall
+  auto bounce = [&](int k) -> R {
+    R val = *lane_at(fin, (int64_t)L::opp(k) * p.cells + own, x);
+    if (L::c(k, 1) < 0 && !p.per[1] && y - L::c(k, 1) >= p.n[1])
+      val += R(6 * L::w(k)) * p.rho0 * R(L::c(k, 0)) * p.lid_u;
+    return val;
+  };
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    int64_t row;
+    if (src(k, row))
+      f[k] = __builtin_nontemporal_load(lane_at(fin, (int64_t)k * p.cells + row, px.xs[1 - L::c(k, 0)]));
+    else
+      f[k] = bounce(k);
+  }
+  // lanes whose x source lies behind a wall (the tiles at x = 0 and n0 - 1)
+#pragma unroll
+  for (int side = 0; side < 3; side += 2) {
+    if (px.xw[side]) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        int64_t row;
+        if (1 - L::c(k, 0) == side && src(k, row)) f[k] = bounce(k);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -241,7 +326,7 @@ __device__ __forceinline__ R tdev_at(const KP<R>& p, int c, R ts) {
 // MT: the equilibrium compositions depend on T (some mT != 0); a separate
 // instance keeps the registers of the common case
 template <int D, int Q, int N, int NC, class R, bool SH, bool MT>
-__device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, R ts0,
+__device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, const PullX& px, R ts0,
                                            const R (&ph1n)[2 * D + 1][N],
                                            const R (&mun)[2 * D + 1][NC], const R (&uc)[D],
                                            const R (&un)[D][2], const R (&ph0)[N],
@@ -249,14 +334,18 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
                                            R* __restrict__ u_out, R* __restrict__ fout,
                                            R* __restrict__ dr_out) {
   using L = Lat<Q>;
-  const int64_t P = (int64_t)z * p.sz + (int64_t)y * p.sy + x;
+  const int64_t own = (int64_t)z * p.sz + (int64_t)y * p.sy;  // the cell is own + x
   const int pos[3] = {x, y, z};
-  // T^n - T_E at the cell and at its pull-axis neighbours (slots of ph1n)
+  // T^n - T_E at the cell and at its neighbours (slots of ph1n); only the
+  // neighbours along the pull axis differ from the cell
   const int pa = p.pull_axis;
+  const R tdc = MT ? tdev_at(p, pos[pa], ts0) : R(0);
   auto tdev_slot = [&](int slot) -> R {
     if constexpr (!MT) return R(0);
-    if (slot == 0 || (slot - 1) / 2 != pa) return tdev_at(p, pos[pa], ts0);
-    return tdev_at(p, nb_field(pos[pa], ((slot - 1) & 1) ? 1 : -1, p.n[pa], p.per[pa]), ts0);
+    if (slot == 0) return tdc;
+    const int a = (slot - 1) / 2;
+    if (a != pa) return tdc;
+    return tdev_at(p, nb_field(pos[a], ((slot - 1) & 1) ? 1 : -1, p.n[a], p.per[a]), ts0);
   };
 
   // per-cell quantities at phi^{n+1}: c* = sum h C(mu^n, T^n), M = sum phi D chi
@@ -292,8 +381,8 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
   R divJ[NC];
 #pragma unroll
   for (int i = 0; i < NC; ++i) divJ[i] = R(0);
-  const R conv = p.dx / p.dt;  // lattice velocity -> phase-field units
-  const R idx = R(1) / p.dx;
+  const R conv = p.conv;  // lattice velocity -> phase-field units
+  const R idx = p.idx;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
 #pragma unroll
@@ -353,12 +442,11 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
     mn[NC - 1] = mun[0][NC - 1] + (-a21 * Dl[0] + a11 * Dl[NC - 1]) / det;
   }
 #pragma unroll
-  for (int i = 0; i < NC; ++i) __builtin_nontemporal_store(mn[i], &mu_out[i * p.cells + P]);
+  for (int i = 0; i < NC; ++i) __builtin_nontemporal_store(mn[i], lane_at(mu_out, i * p.cells + own, x));
 
   // ---- LBM: pull streaming of the previous post-collision populations ----
   R f[L::Q];
-#pragma unroll
-  for (int k = 0; k < L::Q; ++k) f[k] = pull_f<D, Q, R>(p, fin, x, y, z, P, k);
+  pull_row<D, Q, R>(p, fin, x, y, z, px, f);
   // moments (deviation storage: rho = rho0 + sum f~, momentum = sum f~ c)
   R dr = R(0), mom[D];
 #pragma unroll
@@ -371,7 +459,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
       if (L::c(k, a) != 0) mom[a] += R(L::c(k, a)) * f[k];
   }
   const R rho = p.rho0 + dr;
-  if (dr_out) dr_out[P] = dr;  // kept for the adjoint sweep
+  if (dr_out) *lane_at(dr_out, own, x) = dr;  // kept for the adjoint sweep
   const R phil = ph1[N - 1];
   R bsum = R(0);
 #pragma unroll
@@ -408,10 +496,10 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
   }
   const R sol = (R(1) - phil) * (R(1) - phil);
   R u[D], F[D];
+  const R iu = (phil != R(0)) ? R(1) / (rho * (R(1) + R(0.5) * p.kappa * sol)) : R(0);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    u[a] = (phil != R(0)) ? (mom[a] + R(0.5) * FB[a]) / (rho * (R(1) + R(0.5) * p.kappa * sol))
-                          : R(0);
+    u[a] = (mom[a] + R(0.5) * FB[a]) * iu;
     F[a] = FB[a] - p.kappa * rho * sol * u[a];
   }
   R uu = R(0), uF = R(0);
@@ -420,7 +508,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
     uu += u[a] * u[a];
     uF += u[a] * F[a];
   }
-  const R pref = R(1) - R(0.5) / p.tau_lb;
+  const R pref = p.guo;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
     R cu = R(0), cF = R(0);
@@ -431,12 +519,13 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
         cF += R(L::c(k, a)) * F[a];
       }
     }
-    const R feq = p.w[k] * (dr + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
-    const R S = pref * p.w[k] * (R(3) * (cF - uF) + R(9) * cu * cF);
-    __builtin_nontemporal_store(f[k] - (f[k] - feq) / p.tau_lb + S, &fout[k * p.cells + P]);
+    const R wk = R(L::w(k));
+    const R feq = wk * (dr + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+    const R S = pref * wk * (R(3) * (cF - uF) + R(9) * cu * cF);
+    __builtin_nontemporal_store(f[k] - (f[k] - feq) * p.omega + S, lane_at(fout, k * p.cells + own, x));
   }
 #pragma unroll
-  for (int a = 0; a < D; ++a) __builtin_nontemporal_store(u[a], &u_out[a * p.cells + P]);
+  for (int a = 0; a < D; ++a) __builtin_nontemporal_store(u[a], lane_at(u_out, a * p.cells + own, x));
 }
 
 // coordinate along one axis of a tile-halo cell: periodic axes wrap, walls
@@ -594,6 +683,8 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
 // registers before a plane is computed, so their loads overlap it; one
 // barrier per plane.  Threads past the grid's edge hold the wrapped (periodic)
 // or clamped (wall) column, which only serves as a neighbour.
+// A tile row is one 64-lane wave, so a wave's row y and plane z are uniform:
+// every address is a scalar row offset plus the lane's column.
 // ---------------------------------------------------------------------------
 template <int D, int Q, int N, int NC, class R, int TX, int TY, bool SH, bool MT>
 __global__ void __launch_bounds__(TX * TY)
@@ -601,25 +692,27 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
           R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout, R* __restrict__ dr_out,
           R tshift, int tiles_x, int tiles_y, int zc) {
-  static_assert(TX >= 2 && TY >= 2, "edge threads own one row and one column halo cell at most");
+  static_assert(TX == 64, "one tile row per 64-lane wave");
+  static_assert(TY >= 2, "edge threads own one row and one column halo cell at most");
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
   constexpr int NV = N + NC + 2;  // phi^{n+1}, mu^n, U_x, U_y per tile cell
   constexpr int NB = (D == 3) ? 2 : 1;
   __shared__ R sh[NB][NV][HC];
   const Tile T = tile_of(tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
   const int tid = threadIdx.x;
-  const int lx = tid % TX, ly = tid / TX;
+  const int lx = tid % TX, ly = __builtin_amdgcn_readfirstlane(tid / TX);
   const int x = T.x0 + lx, y = T.y0 + ly;
   const bool own = x < p.n[0] && y < p.n[1];
   const int c0 = (ly + 1) * HX + (lx + 1);
   const int xw = wrap_or_clamp(x, p.n[0], p.per[0]), yw = wrap_or_clamp(y, p.n[1], p.per[1]);
-  const int64_t col = (int64_t)yw * p.sy + xw;
+  const int64_t rowc = (int64_t)yw * p.sy;  // + xw: the thread's column
   // halo cells: 0 the row halo (y0 - 1 or y0 + TY), 1 the column halo (x0 - 1 or x0 + TX)
   const bool hrow = ly == 0 || ly == TY - 1, hcol = lx == 0 || lx == TX - 1;
   const int hy = (ly == 0) ? -1 : TY, hx = (lx == 0) ? -1 : TX;
   const int hi0 = (hy + 1) * HX + (lx + 1), hi1 = (ly + 1) * HX + (hx + 1);
-  const int64_t hoff0 = (int64_t)wrap_or_clamp(T.y0 + hy, p.n[1], p.per[1]) * p.sy + xw;
-  const int64_t hoff1 = (int64_t)yw * p.sy + wrap_or_clamp(T.x0 + hx, p.n[0], p.per[0]);
+  const int64_t hrow0 = (int64_t)wrap_or_clamp(T.y0 + hy, p.n[1], p.per[1]) * p.sy;  // + xw
+  const int hx1 = wrap_or_clamp(T.x0 + hx, p.n[0], p.per[0]);                        // + rowc
+  const PullX px = pull_x(x, p.n[0], p.per[0]);
   auto zoff = [&](int zz) -> int64_t {
     return (D == 3) ? (int64_t)wrap_or_clamp(zz, p.n[2], p.per[2]) * p.sz : 0;
   };
@@ -627,30 +720,31 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
   // own column, planes z-1 (index 0), z (1), z+1 (2)
   R cph[3][N], cmu[3][NC], cuz[3];
   auto fetch_col = [&](int zz, R (&ph)[N], R (&m)[NC], R& uz) {
-    const int64_t j = zoff(zz) + col;
+    const int64_t j = zoff(zz) + rowc;
 #pragma unroll
-    for (int q = 0; q < N; ++q) ph[q] = phi1[q * p.cells + j];
+    for (int q = 0; q < N; ++q) ph[q] = *lane_at(phi1, q * p.cells + j, xw);
 #pragma unroll
-    for (int q = 0; q < NC; ++q) m[q] = mu[q * p.cells + j];
-    uz = (D == 3) ? uold[(D - 1) * p.cells + j] : R(0);
+    for (int q = 0; q < NC; ++q) m[q] = *lane_at(mu, q * p.cells + j, xw);
+    uz = (D == 3) ? *lane_at(uold, (D - 1) * p.cells + j, xw) : R(0);
   };
   // values of one plane that go to LDS besides the column's phi and mu: own
   // U_x, U_y and the halo cells
   R cuxy[2], hv[2][NV], ph0[N];
   auto fetch_plane = [&](int zz) {
     const int64_t zo = zoff(zz);
-    cuxy[0] = uold[zo + col];
-    cuxy[1] = uold[p.cells + zo + col];
+    cuxy[0] = *lane_at(uold, zo + rowc, xw);
+    cuxy[1] = *lane_at(uold, p.cells + zo + rowc, xw);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (h == 0 ? hrow : hcol) {
-        const int64_t j = zo + (h == 0 ? hoff0 : hoff1);
+        const int64_t j = zo + (h == 0 ? hrow0 : rowc);
+        const int l = (h == 0) ? xw : hx1;
 #pragma unroll
-        for (int q = 0; q < N; ++q) hv[h][q] = phi1[q * p.cells + j];
+        for (int q = 0; q < N; ++q) hv[h][q] = *lane_at(phi1, q * p.cells + j, l);
 #pragma unroll
-        for (int q = 0; q < NC; ++q) hv[h][N + q] = mu[q * p.cells + j];
-        hv[h][N + NC] = uold[j];
-        hv[h][N + NC + 1] = uold[p.cells + j];
+        for (int q = 0; q < NC; ++q) hv[h][N + q] = *lane_at(mu, q * p.cells + j, l);
+        hv[h][N + NC] = *lane_at(uold, j, l);
+        hv[h][N + NC + 1] = *lane_at(uold, p.cells + j, l);
       }
     }
   };
@@ -668,9 +762,9 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
     }
   };
   auto fetch_ph0 = [&](int zz, R (&o)[N]) {
-    const int64_t j = zoff(zz) + col;
+    const int64_t j = zoff(zz) + rowc;
 #pragma unroll
-    for (int q = 0; q < N; ++q) o[q] = phi0[q * p.cells + j];
+    for (int q = 0; q < N; ++q) o[q] = *lane_at(phi0, q * p.cells + j, xw);
   };
 
   if (D == 3) {
@@ -692,11 +786,13 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
       if (D == 3) fetch_col(z + 2, nph, nmu, nuz);
     }
     if (own) {
-      // opaque per plane: keeps the compiler from hoisting the 19 in-plane
-      // neighbour offsets out of the z loop, which would hold them in
-      // registers across it
+      // strides and coordinates opaque per plane: addresses and the other
+      // quantities of the cell are formed anew on every plane instead of being
+      // carried along z (as pointers, one scalar register pair per buffer and
+      // population, or as per-lane values held in vector registers)
+      KP<R> q = p;
       int xq = x, yq = y;
-      asm volatile("" : "+v"(xq), "+v"(yq));
+      asm volatile("" : "+s"(q.cells), "+s"(q.sy), "+s"(q.sz), "+v"(xq), "+s"(yq));
       R ph1n[2 * D + 1][N], mun[2 * D + 1][NC], uc[D], un[D][2];
       const int off[4] = {-1, 1, -HX, HX};
 #pragma unroll
@@ -730,8 +826,8 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
         un[D - 1][0] = cuz[0];
         un[D - 1][1] = cuz[2];
       }
-      mulbm_core<D, Q, N, NC, R, SH, MT>(p, xq, yq, z, tshift, ph1n, mun, uc, un, ph0, fin, mu_out, u_out, fout,
-                                         dr_out);
+      mulbm_core<D, Q, N, NC, R, SH, MT>(q, xq, yq, z, px, tshift, ph1n, mun, uc, un, ph0, fin, mu_out, u_out,
+                                         fout, dr_out);
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {

@@ -198,6 +198,10 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
   k.dtdev = (R)(p.G != 0.0 ? -p.G * p.V : 0.0);
   k.T_E = (R)p.T_E;
   k.tau_lb = (R)p.tau_lb;
+  k.omega = (R)(1.0 / p.tau_lb);
+  k.guo = (R)(1.0 - 0.5 / p.tau_lb);
+  k.idx = (R)(1.0 / c->grid.dx);
+  k.conv = (R)(c->grid.dx / p.dt);
   k.rho0 = (R)p.rho0;
   for (int i = 0; i < 2; ++i) {
     k.gbeta[i] = (R)p.gbeta[i];
