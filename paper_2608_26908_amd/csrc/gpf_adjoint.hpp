@@ -9,8 +9,8 @@
 //               w = chi_tot^{-1} lam mu'                        w, lam mu^n (direct term)
 //   k_adj_muphi faces of the mu update (gather), then the   -> lam mu^n, lam U^{n-1}, lam phi^n, d D,
 //               projection and local phase-field terms         Rbar, d tau
-//   k_adj_vjp   reverse of each face flux / cell term, once  -> per-role contributions, d delta
-//   k_adj_phi2  gather of those contributions               -> lam phi^n
+//   k_adj_vjp   reverse of each face flux / cell term, once  -> their adjoint values, d delta
+//   k_adj_phi2  gather of the contributions they imply      -> lam phi^n
 // k_adj_lbm of step n - 1 does not read lam phi^n, so k_adj_phi2_lbm runs it
 // in the same launch as the gather of step n (used on small grids).
 // Every kernel gathers into the cells it owns: no atomics, deterministic.
@@ -524,13 +524,14 @@ __device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, in
 // ---------------------------------------------------------------------------
 // 4. projection and the local phase-field terms
 // ---------------------------------------------------------------------------
-template <int D, int N, int NC, class R>
+template <int D, int N, int NC, class R, bool ACT>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
             const R* __restrict__ mu0, const R* __restrict__ mu1, const R* __restrict__ u0,
             const R* __restrict__ w, const R* __restrict__ lphi1, const R* __restrict__ t_phil,
             R* __restrict__ lphi0, R* __restrict__ lmu0, R* __restrict__ lu0, R* __restrict__ rbar,
-            uint8_t* __restrict__ rflag, uint8_t* __restrict__ rowflag, R tshift, double* __restrict__ part) {
+            uint8_t* __restrict__ rflag, uint8_t* __restrict__ rowflag, const uint8_t* __restrict__ act,
+            R tshift, double* __restrict__ part) {
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
   int64_t P;
   int x, y, z;
@@ -539,9 +540,17 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
     mu_adj_cell<D, N, NC, R>(p, P, x, y, z, phi0, phi1, mu0, mu1, u0, w, tshift, mubf, Ubf, p1bf, p0bf, gpart);
 #pragma unroll
     for (int a = 0; a < D; ++a) lu0[a * p.cells + P] = Ubf[a];
+    // the active set of phi^n: recorded by the forward recomputation of the
+    // step (ACT), else from phi^n's 9/19-point stencil, which only the
+    // interface cells need otherwise
+    unsigned active = 0u;
     R v[N][3][3][3];
-    load_stencil<D, N, R>(p, phi0, x, y, z, v);
-    const unsigned active = active_of<D, N, R>(v);
+    if constexpr (ACT) {
+      active = act[P];
+    } else {
+      load_stencil<D, N, R>(p, phi0, x, y, z, v);
+      active = active_of<D, N, R>(v);
+    }
     R pb[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) pb[b] = lphi1[b * p.cells + P] + p1bf[b];
@@ -559,6 +568,7 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
 #pragma unroll
       for (int b = 0; b < N; ++b) p0b[b] += pb[b];
     } else {
+      if constexpr (ACT) load_stencil<D, N, R>(p, phi0, x, y, z, v);
       R Rv[N], vv[N], out[N], theta;
       pf_rhs<D, N, NC, R>(p, v, mu0, x, y, z, tshift, Rv);
 #pragma unroll
@@ -659,15 +669,15 @@ __device__ __forceinline__ bool owner_coord(int v, int n, int per, int& out) {
 }
 
 // Reverse of one face flux J_a (left cell L, right cell L + e_a), seeded with
-// Jb[phase].  Roles: 0 L, 1 R, then per tangential axis b (in order): L-e_b,
-// L+e_b, R-e_b, R+e_b.  rc: role coordinates (walls mirrored, wraps applied);
-// contrib: adjoint of phi at each role.  dd: derivative in delta (pairs with
-// delta != 0).
+// Jb[phase]: the adjoints pfb of the face value of phi and grb of its face
+// gradient, which give the contribution to the adjoint of phi at each role
+// cell (0 L, 1 R, then per tangential axis b in order: L-e_b, L+e_b, R-e_b,
+// R+e_b; face_store).  dd: derivative in delta (pairs with delta != 0).
 template <int D, int N, class R>
 __device__ __forceinline__ void face_vjp(const KP<R>& p, const R* __restrict__ phi, const int (&Lc)[3],
-                                         int a, const R (&Jb)[N], int (&rc)[2 + 4 * (D - 1)][3],
-                                         R (&contrib)[2 + 4 * (D - 1)][N], R& dd) {
+                                         int a, const R (&Jb)[N], R (&pfb)[N], R (&grb)[N][D], R& dd) {
   constexpr int NR = 2 + 4 * (D - 1);
+  int rc[NR][3];
   int o[NR][3];
 #pragma unroll
   for (int r = 0; r < NR; ++r) o[r][0] = o[r][1] = o[r][2] = 0;
@@ -694,10 +704,7 @@ __device__ __forceinline__ void face_vjp(const KP<R>& p, const R* __restrict__ p
       rc[r][e] = (e < D) ? nb_field(Lc[e], o[r][e], p.n[e], p.per[e]) : 0;
     const int64_t j = (int64_t)rc[r][2] * p.sz + (int64_t)rc[r][1] * p.sy + rc[r][0];
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      ph[r][b] = phi[b * p.cells + j];
-      contrib[r][b] = R(0);
-    }
+    for (int b = 0; b < N; ++b) ph[r][b] = phi[b * p.cells + j];
   }
   const R idx = R(1) / p.dx, ih2 = R(0.5) / p.dx;
   R pf[N], gr[N][D];
@@ -715,7 +722,6 @@ __device__ __forceinline__ void face_vjp(const KP<R>& p, const R* __restrict__ p
       }
     }
   }
-  R pfb[N], grb[N][D];
 #pragma unroll
   for (int b = 0; b < N; ++b) {
     pfb[b] = R(0);
@@ -749,31 +755,47 @@ __device__ __forceinline__ void face_vjp(const KP<R>& p, const R* __restrict__ p
         grb[al][e] -= qb[e] * pf[be];
       }
     }
+}
+
+// The N (1 + D) values a face (a, L) stores for the gather, from its pfb, grb:
+// k = b: the contribution to phi_b at role 0 (L), N + b: at role 1 (R),
+// 2N + b (D - 1) + t: the one at the roles along the t-th tangential axis,
+// with sign - at L-e, R-e and + at L+e, R+e.
+template <int D, int N, class R>
+__device__ __forceinline__ void face_store(const KP<R>& p, int a, const R (&pfb)[N], const R (&grb)[N][D],
+                                           R* __restrict__ fb, int64_t L) {
+  const R idx = R(1) / p.dx, ih2 = R(0.5) / p.dx;
 #pragma unroll
   for (int b = 0; b < N; ++b) {
-    contrib[0][b] += R(0.5) * pfb[b] - grb[b][a] * idx;
-    contrib[1][b] += R(0.5) * pfb[b] + grb[b][a] * idx;
-    int r = 2;
+    fb[(int64_t)b * p.cells + L] = R(0.5) * pfb[b] - grb[b][a] * idx;
+    fb[(int64_t)(N + b) * p.cells + L] = R(0.5) * pfb[b] + grb[b][a] * idx;
+    int t = 0;
 #pragma unroll
     for (int e = 0; e < D; ++e) {
       if (e == a) continue;
-      const R gcb = R(0.5) * grb[b][e] * ih2;
-      contrib[r][b] -= gcb;
-      contrib[r + 1][b] += gcb;
-      contrib[r + 2][b] -= gcb;
-      contrib[r + 3][b] += gcb;
-      r += 4;
+      fb[(int64_t)(2 * N + b * (D - 1) + t) * p.cells + L] = R(0.5) * grb[b][e] * ih2;
+      ++t;
     }
   }
 }
+// Contribution of face (a, L) to the adjoint of phi_b at its role cell r
+template <int D, int N, class R>
+__device__ __forceinline__ R face_role(const KP<R>& p, const R* __restrict__ fb, int r, int b, int64_t L) {
+  if (r < 2) return fb[(int64_t)(r * N + b) * p.cells + L];
+  const int t = (r - 2) / 4, k = (r - 2) % 4;
+  const R g = fb[(int64_t)(2 * N + b * (D - 1) + t) * p.cells + L];
+  return (k % 2) ? g : -g;
+}
 
-// Reverse of the cell-centre term at P seeded with cb = -eps Rbar(P).
-// Roles: 0 P, then per axis b: P-e_b, P+e_b.
+// Reverse of the cell-centre term at P seeded with cb = -eps Rbar(P): the
+// adjoints phb of phi at P and gcb of its central gradient, which give the
+// contribution at each role cell (0 P, then per axis b: P-e_b, P+e_b;
+// cell_store).
 template <int D, int N, class R>
 __device__ __forceinline__ void cell_vjp(const KP<R>& p, const R* __restrict__ phi, const int (&Pc)[3],
-                                         const R (&cb)[N], int (&rc)[1 + 2 * D][3],
-                                         R (&contrib)[1 + 2 * D][N], R& dd) {
+                                         const R (&cb)[N], R (&phb)[N], R (&gcb)[N][D], R& dd) {
   constexpr int NR = 1 + 2 * D;
+  int rc[NR][3];
   R ph[NR][N];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -785,13 +807,10 @@ __device__ __forceinline__ void cell_vjp(const KP<R>& p, const R* __restrict__ p
     }
     const int64_t j = (int64_t)rc[r][2] * p.sz + (int64_t)rc[r][1] * p.sy + rc[r][0];
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      ph[r][b] = phi[b * p.cells + j];
-      contrib[r][b] = R(0);
-    }
+    for (int b = 0; b < N; ++b) ph[r][b] = phi[b * p.cells + j];
   }
   const R ih2 = R(0.5) / p.dx;
-  R gc[N][D], gcb[N][D], phb[N];
+  R gc[N][D];
 #pragma unroll
   for (int b = 0; b < N; ++b) {
     phb[b] = R(0);
@@ -829,28 +848,42 @@ __device__ __forceinline__ void cell_vjp(const KP<R>& p, const R* __restrict__ p
         gcb[al][e] -= qb[e] * ph[0][be];
       }
     }
+}
+
+// The N (1 + D) values the cell term at P stores for the gather: k = b: the
+// contribution to phi_b at role 0 (P), N + b D + e: the one at P+e_e (at
+// P-e_e with sign -).
+template <int D, int N, class R>
+__device__ __forceinline__ void cell_store(const KP<R>& p, const R (&phb)[N], const R (&gcb)[N][D],
+                                           R* __restrict__ cb, int64_t P) {
+  const R ih2 = R(0.5) / p.dx;
 #pragma unroll
   for (int b = 0; b < N; ++b) {
-    contrib[0][b] += phb[b];
+    cb[(int64_t)b * p.cells + P] = phb[b];
 #pragma unroll
-    for (int e = 0; e < D; ++e) {
-      contrib[1 + 2 * e][b] -= gcb[b][e] * ih2;
-      contrib[2 + 2 * e][b] += gcb[b][e] * ih2;
-    }
+    for (int e = 0; e < D; ++e) cb[(int64_t)(N + b * D + e) * p.cells + P] = gcb[b][e] * ih2;
   }
+}
+// Contribution of the cell term at P to the adjoint of phi_b at its role cell r
+template <int D, int N, class R>
+__device__ __forceinline__ R cell_role(const KP<R>& p, const R* __restrict__ cb, int r, int b, int64_t P) {
+  if (r == 0) return cb[(int64_t)b * p.cells + P];
+  const int e = (r - 1) / 2;
+  const R g = cb[(int64_t)(N + b * D + e) * p.cells + P];
+  return ((r - 1) % 2) ? g : -g;
 }
 
 // 5a. Writer: every cell computes, once, the reverse of the face fluxes it
-// owns (its +e_a faces) and of its cell-centre term, and stores the
-// contributions per role: fbuf[(a NRF + r) N + b][L], cbuf[(r N + b)][P].
-// Only entries with a non-zero seed are written; fflag[a][L] / rflag[P]
-// (written by k_adj_muphi) say which.
+// owns (its +e_a faces) and of its cell-centre term, and stores the N (1 + D)
+// values that give their contributions at the role cells: fbuf[a NFV + k][L],
+// cbuf[k][P] (face_store, cell_store).  Only entries with a non-zero seed are
+// written; fflag[a][L] / rflag[P] (written by k_adj_muphi) say which.
 template <int D, int N, int NC, class R>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
           const uint8_t* __restrict__ rflag, R* __restrict__ fbuf, uint8_t* __restrict__ fflag,
           R* __restrict__ cbuf, double* __restrict__ part, const uint8_t* __restrict__ rowflag, int split) {
-  constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
+  constexpr int NFV = N * (1 + D);
   double gpart[NG] = {0, 0, 0, 0, 0, 0};
   // split: D + 1 linear grids side by side, grid a < D for the faces along a,
   // grid D for the cell terms (more waves in flight on small grids); else
@@ -897,14 +930,10 @@ k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
             any = any || (Jb[b] != R(0));
           }
           if (any) {
-            int rc[NRF][3];
-            R contrib[NRF][N], dd;
-            face_vjp<D, N, R>(p, phi0, Lc, a, Jb, rc, contrib, dd);
+            R pfb[N], grb[N][D], dd;
+            face_vjp<D, N, R>(p, phi0, Lc, a, Jb, pfb, grb, dd);
             dd_sum += dd;
-#pragma unroll
-            for (int r = 0; r < NRF; ++r)
-#pragma unroll
-              for (int b = 0; b < N; ++b) fbuf[((int64_t)(a * NRF + r) * N + b) * p.cells + L] = contrib[r][b];
+            face_store<D, N, R>(p, a, pfb, grb, fbuf + (int64_t)a * NFV * p.cells, L);
             flag = 1;
           }
         }
@@ -915,14 +944,10 @@ k_adj_vjp(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ rbar,
       R cbv[N];
 #pragma unroll
       for (int b = 0; b < N; ++b) cbv[b] = -p.eps * rl[b];
-      int rc[NRC][3];
-      R contrib[NRC][N], dd;
-      cell_vjp<D, N, R>(p, phi0, Lc, cbv, rc, contrib, dd);
+      R phb[N], gcb[N][D], dd;
+      cell_vjp<D, N, R>(p, phi0, Lc, cbv, phb, gcb, dd);
       dd_sum += dd;
-#pragma unroll
-      for (int r = 0; r < NRC; ++r)
-#pragma unroll
-        for (int b = 0; b < N; ++b) cbuf[((int64_t)r * N + b) * p.cells + L] = contrib[r][b];
+      cell_store<D, N, R>(p, phb, gcb, cbuf, L);
     }
     gpart[G_DELTA] = (double)dd_sum;
   }
@@ -955,7 +980,7 @@ __device__ __forceinline__ void adj_phi2_cell(const KP<R>& p, const int64_t X, c
                                               const uint8_t* __restrict__ fflag, const R* __restrict__ cbuf,
                                               R* __restrict__ lphi0, const uint8_t* __restrict__ rowflag,
                                               uint8_t* __restrict__ rowclear) {
-  constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D;
+  constexpr int NRF = 2 + 4 * (D - 1), NRC = 1 + 2 * D, NFV = N * (1 + D);
   if (xc[0] == 0) rowclear[(int64_t)xc[2] * p.n[1] + xc[1]] = 0;
   // no seed in the 3 x 3 rows (y, z) around the cell: nothing to gather
   bool row_any = false;
@@ -1021,12 +1046,13 @@ __device__ __forceinline__ void adj_phi2_cell(const KP<R>& p, const int64_t X, c
       for (int r = 0; r < NRF; ++r)
         if (ff[a][r])
 #pragma unroll
-          for (int b = 0; b < N; ++b) acc[b] += fbuf[((int64_t)(a * NRF + r) * N + b) * p.cells + Lj[a][r]];
+          for (int b = 0; b < N; ++b)
+            acc[b] += face_role<D, N, R>(p, fbuf + (int64_t)a * NFV * p.cells, r, b, Lj[a][r]);
 #pragma unroll
     for (int r = 0; r < NRC; ++r)
       if (cf[r])
 #pragma unroll
-        for (int b = 0; b < N; ++b) acc[b] += cbuf[((int64_t)r * N + b) * p.cells + Pj[r]];
+        for (int b = 0; b < N; ++b) acc[b] += cell_role<D, N, R>(p, cbuf, r, b, Pj[r]);
 #pragma unroll
     for (int b = 0; b < N; ++b) lphi0[b * p.cells + X] += acc[b];
     return;
@@ -1051,7 +1077,7 @@ __device__ __forceinline__ void adj_phi2_cell(const KP<R>& p, const int64_t X, c
         for (int e = 0; e < D; ++e)
           hit = hit && (nb_field(Lc[e], face_role_off<D>(a, r, e), p.n[e], p.per[e]) == xc[e]);
         if (hit)
-          for (int b = 0; b < N; ++b) acc[b] += fbuf[((int64_t)(a * NRF + r) * N + b) * p.cells + Lj];
+          for (int b = 0; b < N; ++b) acc[b] += face_role<D, N, R>(p, fbuf + (int64_t)a * NFV * p.cells, r, b, Lj);
       }
     }
   }
@@ -1080,7 +1106,7 @@ __device__ __forceinline__ void adj_phi2_cell(const KP<R>& p, const int64_t X, c
           hit = hit && (nb_field(Pc[e], off, p.n[e], p.per[e]) == xc[e]);
         }
         if (hit)
-          for (int b = 0; b < N; ++b) acc[b] += cbuf[((int64_t)r * N + b) * p.cells + Pj];
+          for (int b = 0; b < N; ++b) acc[b] += cell_role<D, N, R>(p, cbuf, r, b, Pj);
       }
     }
   }

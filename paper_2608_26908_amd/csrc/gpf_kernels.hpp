@@ -286,12 +286,14 @@ __device__ __forceinline__ void pf_rhs(const KP<R>& p, const R (&v)[N][3][3][3],
 
 // phi^{n+1} of a cell from its neighbourhood v and mu^n: unchanged when one
 // phase is active (bulk, returned true), else the projection of
-// phi + dt/(tau eps) R over the active phases onto the simplex.
+// phi + dt/(tau eps) R over the active phases onto the simplex.  act_out, if
+// not null, receives the cell's active set.
 template <int D, int N, int NC, class R>
 __device__ __forceinline__ bool phi_from_stencil(const KP<R>& p, const R (&v)[N][3][3][3],
                                                  const R* __restrict__ mu, int x, int y, int z,
-                                                 R tshift, R (&res)[N]) {
+                                                 R tshift, R (&res)[N], uint8_t* __restrict__ act_out) {
   const unsigned active = active_of<D, N, R>(v);
+  if (act_out) *act_out = (uint8_t)active;
   if (__builtin_popcount(active) <= 1) {  // bulk: phi unchanged
 #pragma unroll
     for (int b = 0; b < N; ++b) res[b] = v[b][1][1][1];
@@ -564,11 +566,11 @@ __device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty
 // computed and stored to the ring after it, so its loads are in flight during
 // the computation; one barrier per plane.
 // ---------------------------------------------------------------------------
-template <int D, int N, int NC, class R, int TX, int TY>
+template <int D, int N, int NC, class R, int TX, int TY, bool ACT>
 __global__ void __launch_bounds__(TX * TY)
 k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
-        const uint8_t* __restrict__ bulk_in, uint8_t* __restrict__ bulk_out, R tshift, int tiles_x, int tiles_y,
-        int zc) {
+        const uint8_t* __restrict__ bulk_in, uint8_t* __restrict__ bulk_out, uint8_t* __restrict__ act_out,
+        R tshift, int tiles_x, int tiles_y, int zc) {
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
   constexpr int NT = TX * TY, PER = (HC + NT - 1) / NT;  // halo-tile cells per thread
   constexpr int NS = (D == 3) ? 4 : 1;
@@ -584,6 +586,9 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
   // the step that produced phi^n from phi^{n-1}, so phi_out, which still holds
   // phi^{n-1}, already holds phi^n there, and a cell that is bulk again (phi^{n+1}
   // = phi^n) need not be stored.  bulk_out[block] records the same for this step.
+  // ACT (recomputation for the adjoint): act_out receives each cell's active
+  // set of phases, which the reverse of the step reads instead of phi^n's
+  // stencil (an instance of its own keeps the registers of the common case)
   const bool was_bulk = bulk_in && bulk_in[blockIdx.x];
   int all_bulk = 1;
 
@@ -629,7 +634,9 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
           for (int q = 0; q < N; ++q) v[q][dz + 1][dy + 1][dx + 1] = ring[sl[dz + 1]][q][c0 + dy * HX + dx];
         }
     R res[N];
-    const bool bulk = phi_from_stencil<D, N, NC, R>(p, v, mu, xq, yq, z, tshift, res);
+    uint8_t* ap = nullptr;
+    if constexpr (ACT) ap = act_out + (int64_t)z * p.sz + (uint32_t)(yq * (int)p.sy + xq);  // a plane < 2^32 cells
+    const bool bulk = phi_from_stencil<D, N, NC, R>(p, v, mu, xq, yq, z, tshift, res, ap);
     all_bulk &= bulk ? 1 : 0;
     if (was_bulk && bulk) return;
     const int64_t P = (int64_t)z * p.sz + (int64_t)yq * p.sy + xq;

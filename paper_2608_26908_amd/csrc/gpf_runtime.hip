@@ -77,6 +77,7 @@ struct gpf_ctx {
   // the other on a second stream (default priority)
   std::vector<StateBuf> tape[2];
   DevBuf tape_f[2][2];             // populations of each tape's states, alternating
+  DevBuf tape_act[2];              // active set of phi per cell of each recomputed step (bytes)
   hipStream_t side = nullptr;
   hipEvent_t ev_free[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
   StateBuf lam[2];                 // adjoint state (phi, mu, U, post-streaming f)
@@ -333,7 +334,7 @@ struct Impl {
   // state buffer into the other (null elsewhere)
   static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& in, const SP& out, R ts,
                           hipStream_t st, hipEvent_t* ev, const uint8_t* bulk_in = nullptr,
-                          uint8_t* bulk_out = nullptr) {
+                          uint8_t* bulk_out = nullptr, uint8_t* act_out = nullptr) {
     constexpr int TX = 64, TY = kTileY;
     const int tiles_x = (int)((c->n[0] + TX - 1) / TX), tiles_y = (int)((c->n[1] + TY - 1) / TY);
     auto grid = [&](int zc) {
@@ -342,8 +343,12 @@ struct Impl {
     };
     const dim3 block(TX * TY);
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY>), grid(kZChunkPhi), block, 0, st, k, in.phi,
-                       in.mu, out.phi, bulk_in, bulk_out, ts, tiles_x, tiles_y, kZChunkPhi);
+    if (act_out)
+      hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, true>), grid(kZChunkPhi), block, 0, st, k, in.phi,
+                         in.mu, out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, kZChunkPhi);
+    else
+      hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, false>), grid(kZChunkPhi), block, 0, st, k, in.phi,
+                         in.mu, out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, kZChunkPhi);
     if (ev) (void)hipEventRecord(ev[1], st);
 #define GPF_MULBM(SH, MT)                                                                                     \
   hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, SH, MT>), grid(kZChunkMu), block, 0, st, k, in.phi, \
@@ -670,13 +675,20 @@ struct Impl {
                          x1.phi, x1.mu, P(li.f), P(li.u), P(li.mu), P(lo.f), P(c->t_phil), P(c->t_w), P(lo.mu),
                          ts1, a.part);
   }
+  // act: the active sets of phi^n recorded by the recomputation of step n, or null
   static void adj_muphi_vjp(gpf_ctx* c, const gpf::KP<R>& k, const SP& x0, const SP& x1, int64_t n,
-                            StateBuf& li, StateBuf& lo) {
+                            StateBuf& li, StateBuf& lo, const uint8_t* act) {
     const AdjLaunch a = adj_launch(c);
-    hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R>), a.g, a.b, 0, c->stream, k, x0.phi, x1.phi,
-                       x0.mu, x1.mu, x0.u, P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
-                       P(lo.mu), P(lo.u), P(c->t_rbar), a.rflag, rowflags(c, n), (R)tshift(c, n),
-                       a.part + a.pstride);
+    if (act)
+      hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R, true>), a.g, a.b, 0, c->stream, k, x0.phi, x1.phi,
+                         x0.mu, x1.mu, x0.u, P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
+                         P(lo.mu), P(lo.u), P(c->t_rbar), a.rflag, rowflags(c, n), act, (R)tshift(c, n),
+                         a.part + a.pstride);
+    else
+      hipLaunchKernelGGL((gpf::k_adj_muphi<D, N, NC, R, false>), a.g, a.b, 0, c->stream, k, x0.phi, x1.phi,
+                         x0.mu, x1.mu, x0.u, P(c->t_w), P(li.phi), P(c->t_phil), P(lo.phi),
+                         P(lo.mu), P(lo.u), P(c->t_rbar), a.rflag, rowflags(c, n), act, (R)tshift(c, n),
+                         a.part + a.pstride);
     const int split = small_grid(c) ? 1 : 0;
     hipLaunchKernelGGL((gpf::k_adj_vjp<D, N, NC, R>), dim3(a.g.x * (split ? D + 1 : 1)), a.b, 0, c->stream, k,
                        x0.phi, P(c->t_rbar), a.rflag, P(c->t_fbuf), a.fflag, P(c->t_cbuf), a.part + 2 * a.pstride,
@@ -731,8 +743,9 @@ struct Impl {
       if (!rc) rc = dev_alloc(c, c->t_rflag, (size_t)c->cells);
       if (!rc) rc = dev_alloc(c, c->t_rowflag, (size_t)2 * c->n[1] * c->n[2]);
       if (!rc) rc = dev_alloc(c, c->t_fflag, (size_t)D * c->cells);
-      if (!rc) rc = dev_alloc(c, c->t_fbuf, (size_t)D * (2 + 4 * (D - 1)) * N * cs);
-      if (!rc) rc = dev_alloc(c, c->t_cbuf, (size_t)(1 + 2 * D) * N * cs);
+      // reverse of the face fluxes and cell terms: N (1 + D) values per face / cell
+      if (!rc) rc = dev_alloc(c, c->t_fbuf, (size_t)D * N * (1 + D) * cs);
+      if (!rc) rc = dev_alloc(c, c->t_cbuf, (size_t)N * (1 + D) * cs);
       if (rc) return rc;
     }
     const int64_t nseg = (total + K - 1) / K;
@@ -755,6 +768,11 @@ struct Impl {
         int r;
         if (!c->tape_f[b][i].ptr && (r = dev_alloc(c, c->tape_f[b][i], Q * cs))) return r;
       }
+      const size_t act_bytes = (size_t)(K - 1) * (size_t)c->cells;
+      if (K > 1 && c->tape_act[b].bytes < act_bytes) {
+        dev_release(c, c->tape_act[b]);
+        if (int r = dev_alloc(c, c->tape_act[b], act_bytes)) return r;
+      }
       return GPF_OK;
     };
     // tape 0; with several segments, tape 1 for recomputing the previous
@@ -775,6 +793,7 @@ struct Impl {
         c->tape[1].clear();
         dev_release(c, c->tape_f[1][0]);
         dev_release(c, c->tape_f[1][1]);
+        dev_release(c, c->tape_act[1]);
         (void)hipGetLastError();  // a failed hipMalloc leaves its error behind
         c->err.clear();
       }
@@ -817,9 +836,12 @@ struct Impl {
       return s;
     };
     auto seg_len = [&](int64_t sg) { return std::min<int64_t>(K, total - sg * K); };
-    // step j of the recomputation of segment sg into tape b
+    // step j of the recomputation of segment sg into tape b; it also records
+    // the active sets of phi^{n0 + j} (j < K - 1)
+    auto act_of = [&](int b, int64_t j) { return static_cast<uint8_t*>(c->tape_act[b].ptr) + j * c->cells; };
     auto recompute_step = [&](int b, int64_t sg, int64_t j, hipStream_t st) {
-      launch_step(c, k, slot(b, sg, j), slot(b, sg, j + 1), (R)tshift(c, c->rec_start + sg * K + j), st, nullptr);
+      launch_step(c, k, slot(b, sg, j), slot(b, sg, j + 1), (R)tshift(c, c->rec_start + sg * K + j), st, nullptr,
+                  nullptr, nullptr, act_of(b, j));
     };
     auto tape_of = [&](int64_t sg) { return ntape == 2 ? (int)((nseg - 1 - sg) & 1) : 0; };
     // X^{rec_start + m}, m in [0, total]: the checkpoints every K steps, the
@@ -855,7 +877,10 @@ struct Impl {
           HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->ev_free[1 - b], 0));
         }
       }
-      adj_muphi_vjp(c, k, state(m), state(m + 1), c->rec_start + m, *li, *lo);
+      // the active sets of step m were recorded unless its successor is a
+      // checkpoint or the final state (the step was not recomputed)
+      const uint8_t* act = (j < seg_len(sg) - 1) ? act_of(b, j) : nullptr;
+      adj_muphi_vjp(c, k, state(m), state(m + 1), c->rec_start + m, *li, *lo, act);
       if (jr < nrec) recompute_step(1 - b, sg - 1, jr++, c->side);
       if (m > 0) {
         if (j == 0 && ntape == 2) {
@@ -1135,6 +1160,7 @@ void free_all(gpf_ctx* c) {
     c->tape[b].clear();
     dev_release(c, c->tape_f[b][0]);
     dev_release(c, c->tape_f[b][1]);
+    dev_release(c, c->tape_act[b]);
   }
   for (int b = 0; b < 2; ++b) {
     if (c->ev_free[b]) (void)hipEventDestroy(c->ev_free[b]);
