@@ -85,6 +85,12 @@ struct gpf_ctx {
   DevBuf t_rowflag;                // per (y, z) row seed flags, two step parities
   int lam_cur = 0;                 // lam[lam_cur] holds the adjoint of the earliest state reached
   bool have_adjoint = false;
+  // graph replay of kGraphSteps steps on small grids, one per starting buffer
+  // set, valid while the kernel parameter block and shift it was captured
+  // with are unchanged; captured on a stream of the library's own
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::string gkey[2];
 };
 
 namespace {
@@ -410,6 +416,58 @@ struct Impl {
     return GPF_OK;
   }
 
+  // Small grids: a step is two launches of a few microseconds, and the gaps
+  // between launches are a sizeable part of it.  Runs of kGraphSteps steps
+  // whose kernels see the same arguments every step (no pulled temperature in
+  // motion, no moving frame, health check or recording) replay one captured
+  // graph of them instead; its first step does not use the bulk history, so
+  // the graph holds whatever state the buffers hold.
+  static constexpr int64_t kGraphSteps = 64;
+  static bool graph_eligible(const gpf_ctx* c, bool timed) {
+    return small_grid(c) && !timed && c->prm.frame_every == 0 && c->prm.health_every == 0 && c->rec_every == 0 &&
+           (c->prm.G == 0.0 || c->prm.V == 0.0);
+  }
+  // kGraphSteps steps from the current state by graph replay; *done false when
+  // no graph could be used (nothing was queued then)
+  static int graph_steps(gpf_ctx* c, const gpf::KP<R>& k, int64_t remaining, bool* done) {
+    *done = false;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (c->stream && hipStreamIsCapturing(c->stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+      return GPF_OK;  // the caller is capturing: its graph records the plain launches
+    const int s = c->cur, t = 1 - c->cur;
+    const R ts = (R)tshift(c, c->step);
+    std::string key(reinterpret_cast<const char*>(&k), sizeof(k));
+    if (k.G != R(0)) key.append(reinterpret_cast<const char*>(&ts), sizeof(ts));
+    if (!c->gexec[s] || c->gkey[s] != key) {
+      if (remaining < 2 * kGraphSteps) return GPF_OK;  // not worth a capture
+      if (c->gexec[s]) {
+        (void)hipGraphExecDestroy(c->gexec[s]);
+        c->gexec[s] = nullptr;
+      }
+      if (!c->gstream) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+      HIP_OR_FAIL(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+      for (int64_t j = 0; j < kGraphSteps; ++j) {
+        const int a = (s + (int)j) & 1, b = 1 - a;
+        launch_step(c, k, cur(c, a), cur(c, b), ts, c->gstream, nullptr,
+                    j ? static_cast<const uint8_t*>(c->bulkf[a].ptr) : nullptr, static_cast<uint8_t*>(c->bulkf[b].ptr));
+      }
+      hipGraph_t g = nullptr;
+      HIP_OR_FAIL(c, hipStreamEndCapture(c->gstream, &g));
+      const hipError_t e = hipGraphInstantiate(&c->gexec[s], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        c->gexec[s] = nullptr;
+        return fail(c, GPF_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+      }
+      c->gkey[s] = key;
+    }
+    HIP_OR_FAIL(c, hipGraphLaunch(c->gexec[s], c->stream));
+    c->bulk_ok[s] = c->bulk_ok[t] = true;
+    c->step += kGraphSteps;  // an even count: the state is back in buffer set s
+    *done = true;
+    return GPF_OK;
+  }
+
   static int step(gpf_ctx* c, int64_t nsteps, double* kernel_ms, int nk) {
     gpf::KP<R> k = make_kp<R>(c);
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -418,7 +476,16 @@ struct Impl {
       for (int i = 0; i < nk; ++i) kernel_ms[i] = 0.0;
     }
     const int64_t H = c->prm.health_every;
+    const bool graphs = graph_eligible(c, kernel_ms != nullptr);
     for (int64_t it = 0; it < nsteps; ++it) {
+      if (graphs && nsteps - it >= kGraphSteps) {
+        bool done = false;
+        if (int rc = graph_steps(c, k, nsteps - it, &done)) return rc;
+        if (done) {
+          it += kGraphSteps - 1;
+          continue;
+        }
+      }
       const int s = c->cur, t = 1 - c->cur;
       const R ts = (R)tshift(c, c->step);
       launch_step(c, k, cur(c, s), cur(c, t), ts, c->stream, kernel_ms ? ev : nullptr,
@@ -1180,6 +1247,14 @@ void free_all(gpf_ctx* c) {
   dev_release(c, c->t_fflag);
   dev_release(c, c->t_fbuf);
   dev_release(c, c->t_cbuf);
+  for (int b = 0; b < 2; ++b) {
+    if (c->gexec[b]) (void)hipGraphExecDestroy(c->gexec[b]);
+    c->gexec[b] = nullptr;
+  }
+  if (c->gstream) {
+    (void)hipStreamDestroy(c->gstream);
+    c->gstream = nullptr;
+  }
 }
 
 int set_named(gpf_ctx* c, gpf_params& p, const char* name, double v) {
