@@ -781,6 +781,30 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
   fetch_col(T.z0, cph[1], cmu[1], cuz[1]);
   fetch_plane(T.z0);
   fetch_ph0(T.z0, ph0);
+  {
+    // every value loaded before the loop is consumed here, so none is still
+    // in flight when the loop starts: the loop's own prefetch is then waited
+    // for where the next plane uses it, not (as the compiler's wait counting
+    // would otherwise place it, merging the loop's entry with its back edge)
+    // at the first use of a value carried into the loop, in mid-plane
+    auto settle = [](R& v) { asm volatile("" : "+v"(v)); };
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) settle(cph[k][q]);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) settle(cmu[k][q]);
+      settle(cuz[k]);
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) settle(ph0[q]);
+    settle(cuxy[0]);
+    settle(cuxy[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) settle(hv[h][v]);
+  }
   for (int z = T.z0; z < T.z1; ++z) {
     const int bf = (z - T.z0) & (NB - 1);
     write_plane(bf);
