@@ -136,20 +136,27 @@ __device__ __forceinline__ void pull_row(const KP<R>& p, const R* __restrict__ f
 // ---------------------------------------------------------------------------
 // Active set of a cell: bit b set when phase b is non-zero somewhere in the
 // 9/19-point neighbourhood v[phase][dz+1][dy+1][dx+1].
+// Phase b is non-zero somewhere exactly when its largest value over the
+// neighbourhood is positive (one max per value instead of a compare and a
+// select).
 template <int D, int N, class R>
 __device__ __forceinline__ unsigned active_of(const R (&v)[N][3][3][3]) {
   unsigned active = 0u;
 #pragma unroll
-  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+  for (int b = 0; b < N; ++b) {
+    R m = v[b][1][1][1];
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
+    for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
 #pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (dx != 0 && dy != 0 && dz != 0) continue;
+      for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-        for (int b = 0; b < N; ++b)
-          if (v[b][dz + 1][dy + 1][dx + 1] > R(0)) active |= 1u << b;
-      }
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (dx != 0 && dy != 0 && dz != 0) continue;
+          if (dx == 0 && dy == 0 && dz == 0) continue;
+          m = fmax(m, v[b][dz + 1][dy + 1][dx + 1]);
+        }
+    if (m > R(0)) active |= 1u << b;
+  }
   return active;
 }
 
