@@ -139,25 +139,36 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
   using L = Lat<Q>;
   {
     R f[TAPE ? 1 : L::Q], ob[L::Q];
+    // offset of the cell one step along -e_a (index 0) and +e_a (index 1) from
+    // P, wrapped on a periodic axis, and whether that cell lies behind a wall
+    const int pos[3] = {x, y, z};
+    const int64_t stride[3] = {1, p.sy, p.sz};
+    int64_t off[3][2];
+    bool wall[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int si = 0; si < 2; ++si) {
+        const int t = pos[a] + (si ? 1 : -1);
+        wall[a][si] = a < D && !p.per[a] && (t < 0 || t >= p.n[a]);
+        const int w = (t < 0) ? t + p.n[a] : (t >= p.n[a] ? t - p.n[a] : t);
+        off[a][si] = (a < D) ? (int64_t)(w - pos[a]) * stride[a] : 0;
+      }
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
       if constexpr (!TAPE) f[k] = pull_f<D, Q, R>(p, fst, x, y, z, P, k);
       // f*_k(P) streams to f_k(P + c_k), or is reflected into f_{opp k}(P)
-      int dst[3] = {x + L::c(k, 0), y + L::c(k, 1), z + L::c(k, 2)};
+      int64_t dst = P;
       bool in = true;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         if (L::c(k, a) == 0) continue;
-        if (dst[a] < 0 || dst[a] >= p.n[a]) {
-          if (p.per[a])
-            dst[a] = (dst[a] + p.n[a]) % p.n[a];
-          else
-            in = false;
-        }
+        const int si = L::c(k, a) > 0 ? 1 : 0;
+        dst += off[a][si];
+        in = in && !wall[a][si];
       }
       // every adjoint population is read once per reverse step: a streaming load
-      ob[k] = __builtin_nontemporal_load(in ? &lf1[k * p.cells + (int64_t)dst[2] * p.sz + (int64_t)dst[1] * p.sy + dst[0]]
-                                            : &lf1[L::opp(k) * p.cells + P]);
+      ob[k] = __builtin_nontemporal_load(in ? &lf1[k * p.cells + dst] : &lf1[L::opp(k) * p.cells + P]);
     }
     const R phil = phi1[(N - 1) * p.cells + P];
     R mu[NC];
@@ -180,7 +191,6 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
     }
     const R rho = p.rho0 + dr;
     // the liquid's composition at the step's new temperature T^{n+1}
-    const int pos[3] = {x, y, z};
     const R td1 = tdev_at(p, pos[p.pull_axis], tshift1);
     R Cl[NC], bsum = R(0);
 #pragma unroll
@@ -198,19 +208,21 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
     const R sol = (R(1) - phil) * (R(1) - phil);
     const R den = rho * (R(1) + R(0.5) * p.kappa * sol);
     const bool moving = phil != R(0);
+    const R iden = moving ? R(1) / den : R(0);
     R u[D], F[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       if constexpr (TAPE)
         u[a] = u1[a * p.cells + P];
       else
-        u[a] = moving ? (mom[a] + R(0.5) * FB[a]) / den : R(0);
+        u[a] = (mom[a] + R(0.5) * FB[a]) * iden;
       F[a] = FB[a] - p.kappa * rho * sol * u[a];
     }
     R uu = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) uu += u[a] * u[a];
-    const R pref = R(1) - R(0.5) / p.tau_lb;
+    const R pref = p.guo;
+    const R keep = R(1) - p.omega;
     // ---- reverse ----
     R fb[L::Q], drb = R(0), rhob = R(0), uub = R(0), uFb = R(0), ub[D], Fb[D];
 #pragma unroll
@@ -227,14 +239,15 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
           cu += R(L::c(k, a)) * u[a];
           cF += R(L::c(k, a)) * F[a];
         }
-      fb[k] = (R(1) - R(1) / p.tau_lb) * ob[k];
-      const R feqb = ob[k] / p.tau_lb, Sb = ob[k];
-      drb += p.w[k] * feqb;
-      rhob += p.w[k] * feqb * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
-      const R cub = p.w[k] * feqb * rho * (R(3) + R(9) * cu) + R(9) * pref * p.w[k] * Sb * cF;
-      uub += -R(1.5) * p.w[k] * feqb * rho;
-      const R cFb = pref * p.w[k] * Sb * (R(3) + R(9) * cu);
-      uFb += -R(3) * pref * p.w[k] * Sb;
+      const R wk = R(L::w(k));
+      fb[k] = keep * ob[k];
+      const R feqb = ob[k] * p.omega, Sb = ob[k];
+      drb += wk * feqb;
+      rhob += wk * feqb * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+      const R cub = wk * feqb * rho * (R(3) + R(9) * cu) + R(9) * pref * wk * Sb * cF;
+      uub += -R(1.5) * wk * feqb * rho;
+      const R cFb = pref * wk * Sb * (R(3) + R(9) * cu);
+      uFb += -R(3) * pref * wk * Sb;
 #pragma unroll
       for (int a = 0; a < D; ++a)
         if (L::c(k, a) != 0) {
@@ -260,10 +273,10 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
     R mb[D], denb = R(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      mb[a] = moving ? ub[a] / den : R(0);
+      mb[a] = ub[a] * iden;
       if (moving) {
-        FBb[a] += R(0.5) * ub[a] / den;
-        denb += -ub[a] * u[a] / den;
+        FBb[a] += R(0.5) * ub[a] * iden;
+        denb += -ub[a] * u[a] * iden;
       }
     }
     rhob += denb * (R(1) + R(0.5) * p.kappa * sol);
@@ -311,9 +324,9 @@ __device__ __forceinline__ void adj_lbm_cell(const KP<R>& p, const int64_t P, co
     } else {
       const R a11 = sh * p.chi[0][0], a12 = sh * p.chi[0][1];
       const R a21 = sh * p.chi[1][0], a22 = sh * p.chi[1][NC - 1];
-      const R det = a11 * a22 - a12 * a21;
-      w[P] = (a22 * mt[0] - a21 * mt[NC - 1]) / det;
-      w[p.cells + P] = (-a12 * mt[0] + a11 * mt[NC - 1]) / det;
+      const R idet = R(1) / (a11 * a22 - a12 * a21);
+      w[P] = (a22 * mt[0] - a21 * mt[NC - 1]) * idet;
+      w[p.cells + P] = (-a12 * mt[0] + a11 * mt[NC - 1]) * idet;
     }
   }
 }
@@ -390,7 +403,7 @@ __device__ __forceinline__ void mu_adj_cell(const KP<R>& p, int64_t P, int x, in
 #pragma unroll
       for (int k = 0; k < NC; ++k) Mb[i][k] = R(0);
     }
-    const R conv = p.dx / p.dt, idx = R(1) / p.dx, dtdx = p.dt / p.dx;
+    const R conv = p.conv, idx = p.idx, dtdx = p.dt * p.idx;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       Ub[a] = R(0);
@@ -586,12 +599,13 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
         }
       mean = mean / R(ns);
       R vb[N], taub = R(0);
+      const R rtau = -p.rate / p.tau_pf;
 #pragma unroll
       for (int b = 0; b < N; ++b) {
         vb[b] = ((supp >> b) & 1u) ? pb[b] - mean : R(0);
         p0b[b] += vb[b];
         Rb[b] = p.rate * vb[b];
-        taub += vb[b] * Rv[b] * (-p.rate / p.tau_pf);
+        taub += vb[b] * Rv[b] * rtau;
       }
       gpart[G_TAU] += (double)taub;
       // local terms: -dW/dphi / eps and -sum psi dh/dphi
@@ -606,10 +620,10 @@ k_adj_muphi(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
         for (int be = 0; be < N; ++be) {
           if (be == al) continue;
           if (p.potential == 0) {
-            p0b[be] += -Rb[al] * R(1.6211389382774044) * p.gamma[al][be] / p.eps;  // 16 / pi^2
+            p0b[be] += -Rb[al] * R(1.6211389382774044) * p.gamma[al][be] * p.ieps;  // 16 / pi^2
           } else {
-            p0b[al] += -Rb[al] * R(18) * p.gamma[al][be] * ph[be] * ph[be] / p.eps;
-            p0b[be] += -Rb[al] * R(36) * p.gamma[al][be] * ph[al] * ph[be] / p.eps;
+            p0b[al] += -Rb[al] * R(18) * p.gamma[al][be] * ph[be] * ph[be] * p.ieps;
+            p0b[be] += -Rb[al] * R(36) * p.gamma[al][be] * ph[al] * ph[be] * p.ieps;
           }
         }
       const R tdev = (p.G != R(0)) ? p.G * (R((p.pull_axis == 0) ? x : (p.pull_axis == 1 ? y : z)) - tshift)

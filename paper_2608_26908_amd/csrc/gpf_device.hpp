@@ -100,8 +100,8 @@ template <class R> struct KP {
   int tdep;               // some mT != 0 (the compositions depend on T)
   R tau_lb, rho0, gbeta[2], c_ref[2], grav_sign, kappa, lid_u;
   // formed in FP64 on the host: 1 / tau_lb, the Guo prefactor 1 - 1 / (2 tau_lb),
-  // 1 / dx and the lattice-to-phase-field velocity factor dx / dt
-  R omega, guo, idx, conv;
+  // 1 / dx, the lattice-to-phase-field velocity factor dx / dt and 1 / eps
+  R omega, guo, idx, conv, ieps;
   R eta[4];               // shrinkage (rho_a - rho_liq) / rho_liq per phase
   int shrink;             // some eta != 0
   R qmin2;                // |q|^2 below which the anisotropy direction is undefined

@@ -287,7 +287,7 @@ __device__ __forceinline__ void pf_rhs(const KP<R>& p, const R (&v)[N][3][3][3],
     R drive = R(0);
 #pragma unroll
     for (int be = 0; be < N; ++be) drive += ps[be] * dh<N, R>(ph, be, al);
-    Rv[al] = p.eps * (div[al] - cell[al]) - dW / p.eps - drive;
+    Rv[al] = p.eps * (div[al] - cell[al]) - dW * p.ieps - drive;
   }
 }
 

@@ -209,6 +209,7 @@ gpf::KP<R> make_kp(const gpf_ctx* c) {
   k.guo = (R)(1.0 - 0.5 / p.tau_lb);
   k.idx = (R)(1.0 / c->grid.dx);
   k.conv = (R)(c->grid.dx / p.dt);
+  k.ieps = (R)(1.0 / p.eps);
   k.rho0 = (R)p.rho0;
   for (int i = 0; i < 2; ++i) {
     k.gbeta[i] = (R)p.gbeta[i];
