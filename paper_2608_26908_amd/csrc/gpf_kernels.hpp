@@ -549,6 +549,7 @@ __device__ __forceinline__ int wrap_or_clamp(int v, int n, int per) {
 // tiles that are neighbours in y and z share its L2.
 struct Tile {
   int x0, y0, z0, z1;
+  unsigned lb;  // logical tile index: x fastest, then y, then the chunk along z
 };
 __device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty, int zc, int nz,
                                         int D) {
@@ -556,6 +557,7 @@ __device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty
   const unsigned per8 = nb / 8u;
   const unsigned lb = (b < per8 * 8u) ? (b % 8u) * per8 + b / 8u : b;
   Tile t;
+  t.lb = lb;
   t.x0 = (int)(lb % (unsigned)tiles_x) * tx;
   t.y0 = (int)((lb / (unsigned)tiles_x) % (unsigned)tiles_y) * ty;
   const int tz = (int)(lb / ((unsigned)tiles_x * (unsigned)tiles_y));
@@ -588,15 +590,47 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
   const int x = T.x0 + lx, y = T.y0 + ly;
   const bool own = x < p.n[0] && y < p.n[1];
   const int c0 = (ly + 1) * HX + (lx + 1);
-  // Bulk history (both null when phi_out is not the buffer that held phi^{n-1}):
-  // bulk_in[block] says every cell of this block's tile and planes was bulk in
-  // the step that produced phi^n from phi^{n-1}, so phi_out, which still holds
-  // phi^{n-1}, already holds phi^n there, and a cell that is bulk again (phi^{n+1}
-  // = phi^n) need not be stored.  bulk_out[block] records the same for this step.
+  // Bulk history (both null when phi_out is not the buffer that held phi^{n-1}),
+  // one flag per block (logical tile index): bulk_in[block] says every cell of
+  // this block's tile and planes was bulk in the step that produced phi^n from
+  // phi^{n-1}, so phi_out, which still holds phi^{n-1}, already holds phi^n
+  // there, and a cell that is bulk again (phi^{n+1} = phi^n) need not be
+  // stored.  bulk_out[block] records the same for this step.
   // ACT (recomputation for the adjoint): act_out receives each cell's active
   // set of phases, which the reverse of the step reads instead of phi^n's
   // stencil (an instance of its own keeps the registers of the common case)
-  const bool was_bulk = bulk_in && bulk_in[blockIdx.x];
+  if (bulk_in && (D == 3 || p.cells > ((int64_t)1 << 18))) {
+    // If this block and every block its stencils reach (the 26 around it, none
+    // beyond a wall) were bulk in that step, phi^n = phi^{n-1} on every stencil
+    // the block evaluates, so each cell has its previous active set and is
+    // bulk again: phi_out already holds phi^{n+1} = phi^n, nothing to do.  (On
+    // small 2D grids, whose one-plane blocks make a launch of a few
+    // microseconds, the flag loads cost what they save.)
+    int ok = 1;
+    if (tid < 27) {
+      const int d[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
+      const int nt[3] = {tiles_x, tiles_y, (int)(gridDim.x / (unsigned)(tiles_x * tiles_y))};
+      int t3[3] = {(int)(T.lb % (unsigned)tiles_x), (int)((T.lb / (unsigned)tiles_x) % (unsigned)tiles_y),
+                   (int)(T.lb / (unsigned)(tiles_x * tiles_y))};
+      bool exists = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        t3[a] += d[a];
+        if (t3[a] < 0 || t3[a] >= nt[a]) {
+          if (a < D && p.per[a])
+            t3[a] += (t3[a] < 0) ? nt[a] : -nt[a];
+          else
+            exists = false;
+        }
+      }
+      if (exists) ok = bulk_in[t3[0] + tiles_x * (t3[1] + tiles_y * t3[2])];
+    }
+    if (__syncthreads_and(ok)) {
+      if (bulk_out && tid == 0) bulk_out[T.lb] = 1;
+      return;
+    }
+  }
+  const bool was_bulk = bulk_in && bulk_in[T.lb];
   int all_bulk = 1;
 
   // in-plane offsets of this thread's halo-tile cells (fixed along z)
@@ -652,7 +686,7 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
   };
   auto record_bulk = [&]() {
     const int b = __syncthreads_and(all_bulk);
-    if (bulk_out && tid == 0) bulk_out[blockIdx.x] = (uint8_t)b;
+    if (bulk_out && tid == 0) bulk_out[T.lb] = (uint8_t)b;
   };
 
   if (D == 2) {
