@@ -357,6 +357,15 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
     return tdev_at(p, nb_field(pos[a], ((slot - 1) & 1) ? 1 : -1, p.n[a], p.per[a]), ts0);
   };
 
+  // pull streaming of the previous post-collision populations: issued first,
+  // so the loads are in flight during the chemical-potential update, where
+  // that costs no occupancy (FP32, two phases, one solute; elsewhere the
+  // populations held through the update take the kernel past a register
+  // threshold)
+  constexpr bool EARLY = !SH && !MT && N == 2 && NC == 1 && sizeof(R) == 4;
+  R f[L::Q];
+  if constexpr (EARLY) pull_row<D, Q, R>(p, fin, x, y, z, px, f);
+
   // per-cell quantities at phi^{n+1}: c* = sum h C(mu^n, T^n), M = sum phi D chi
   auto quant = [&](int slot, R (&M)[NC][NC], R (&cs)[NC]) {
     const R td = tdev_slot(slot);
@@ -454,8 +463,7 @@ __device__ __forceinline__ void mulbm_core(const KP<R>& p, int x, int y, int z, 
   for (int i = 0; i < NC; ++i) __builtin_nontemporal_store(mn[i], lane_at(mu_out, i * p.cells + own, x));
 
   // ---- LBM: pull streaming of the previous post-collision populations ----
-  R f[L::Q];
-  pull_row<D, Q, R>(p, fin, x, y, z, px, f);
+  if constexpr (!EARLY) pull_row<D, Q, R>(p, fin, x, y, z, px, f);
   // moments (deviation storage: rho = rho0 + sum f~, momentum = sum f~ c)
   R dr = R(0), mom[D];
 #pragma unroll
