@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(TX * TY)
 k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
           R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout, R* __restrict__ dr_out,
-          R tshift, int tiles_x, int tiles_y, int zc) {
+          const uint8_t* __restrict__ phi_bulk, int zc_phi, R tshift, int tiles_x, int tiles_y, int zc) {
   static_assert(TX == 64, "one tile row per 64-lane wave");
   static_assert(TY >= 2, "edge threads own one row and one column halo cell at most");
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
@@ -769,6 +769,19 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
   const int64_t hrow0 = (int64_t)wrap_or_clamp(T.y0 + hy, p.n[1], p.per[1]) * p.sy;  // + xw
   const int hx1 = wrap_or_clamp(T.x0 + hx, p.n[0], p.per[0]);                        // + rowc
   const PullX px = pull_x(x, p.n[0], p.per[0]);
+  // phi_bulk (k_phi_z's flags of this step, null when there are none): where
+  // the k_phi_z block holding this tile and these planes left every cell bulk,
+  // phi^n = phi^{n+1} there, so phi^n is not read (the two-phase FP32
+  // instance, where that saves a phase field per cell at no register cost)
+  constexpr bool SKIP0 = !SH && !MT && N == 2 && NC == 1 && sizeof(R) == 4;
+  bool same0 = false;
+  if constexpr (SKIP0) {
+    if (phi_bulk) {
+      const unsigned tz = (D == 3) ? (unsigned)(T.z0 / zc_phi) : 0u;
+      const unsigned t0 = T.lb % (unsigned)(tiles_x * tiles_y);
+      same0 = phi_bulk[t0 + (unsigned)(tiles_x * tiles_y) * tz] != 0;
+    }
+  }
   auto zoff = [&](int zz) -> int64_t {
     return (D == 3) ? (int64_t)wrap_or_clamp(zz, p.n[2], p.per[2]) * p.sz : 0;
   };
@@ -818,6 +831,7 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
     }
   };
   auto fetch_ph0 = [&](int zz, R (&o)[N]) {
+    if (same0) return;
     const int64_t j = zoff(zz) + rowc;
 #pragma unroll
     for (int q = 0; q < N; ++q) o[q] = *lane_at(phi0, q * p.cells + j, xw);
@@ -906,7 +920,10 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
         un[D - 1][0] = cuz[0];
         un[D - 1][1] = cuz[2];
       }
-      mulbm_core<D, Q, N, NC, R, SH, MT>(q, xq, yq, z, px, tshift, ph1n, mun, uc, un, ph0, fin, mu_out, u_out,
+      R p0[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) p0[k] = same0 ? cph[1][k] : ph0[k];
+      mulbm_core<D, Q, N, NC, R, SH, MT>(q, xq, yq, z, px, tshift, ph1n, mun, uc, un, p0, fin, mu_out, u_out,
                                          fout, dr_out);
     }
 #pragma unroll

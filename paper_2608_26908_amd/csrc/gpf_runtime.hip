@@ -307,6 +307,8 @@ inline unsigned adj_blocks(const int64_t (&n)[3]) {
 #define GPF_ZCHUNK_MU 4
 #endif
 constexpr int kTileY = GPF_TILE_Y, kZChunkPhi = GPF_ZCHUNK_PHI, kZChunkMu = GPF_ZCHUNK_MU;
+// a k_mulbm_z block's planes lie within one k_phi_z block's (its bulk flag applies)
+static_assert(kZChunkPhi % kZChunkMu == 0, "the phase-field plane chunk must be a multiple of the LBM's");
 // blocks of one k_phi_z launch (64 x kTileY tiles, kZChunkPhi planes each in 3D)
 inline int64_t phi_blocks(const gpf_ctx* c) {
   const int64_t tx = (c->n[0] + 63) / 64, ty = (c->n[1] + kTileY - 1) / kTileY;
@@ -359,7 +361,8 @@ struct Impl {
     if (ev) (void)hipEventRecord(ev[1], st);
 #define GPF_MULBM(SH, MT)                                                                                     \
   hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, SH, MT>), grid(kZChunkMu), block, 0, st, k, in.phi, \
-                     out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, ts, tiles_x, tiles_y, kZChunkMu)
+                     out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, bulk_out, kZChunkPhi, ts, tiles_x,    \
+                     tiles_y, kZChunkMu)
     if (k.shrink) {
       if (k.tdep)
         GPF_MULBM(true, true);
