@@ -771,9 +771,9 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
   const PullX px = pull_x(x, p.n[0], p.per[0]);
   // phi_bulk (k_phi_z's flags of this step, null when there are none): where
   // the k_phi_z block holding this tile and these planes left every cell bulk,
-  // phi^n = phi^{n+1} there, so phi^n is not read (the two-phase FP32
-  // instance, where that saves a phase field per cell at no register cost)
-  constexpr bool SKIP0 = !SH && !MT && N == 2 && NC == 1 && sizeof(R) == 4;
+  // phi^n = phi^{n+1} there, so phi^n is not read (the two-phase, one-solute
+  // instances, where that saves a phase field per cell at no register cost)
+  constexpr bool SKIP0 = !SH && !MT && N == 2 && NC == 1;
   bool same0 = false;
   if constexpr (SKIP0) {
     if (phi_bulk) {
