@@ -300,19 +300,29 @@ inline unsigned adj_blocks(const int64_t (&n)[3]) {
 #ifndef GPF_TILE_Y
 #define GPF_TILE_Y 4
 #endif
+#ifndef GPF_ZCHUNK_PHI2
+#define GPF_ZCHUNK_PHI2 8
+#endif
 #ifndef GPF_ZCHUNK_PHI
 #define GPF_ZCHUNK_PHI 16
 #endif
 #ifndef GPF_ZCHUNK_MU
 #define GPF_ZCHUNK_MU 4
 #endif
-constexpr int kTileY = GPF_TILE_Y, kZChunkPhi = GPF_ZCHUNK_PHI, kZChunkMu = GPF_ZCHUNK_MU;
+constexpr int kTileY = GPF_TILE_Y, kZChunkMu = GPF_ZCHUNK_MU;
+// planes per k_phi_z block: two phases spend most of a step in the few blocks
+// that hold the interface, whose plane walk a shorter chunk shortens; three
+// and four phases have interface throughout the solid, where a longer chunk
+// re-reads fewer halo planes
+constexpr int zchunk_phi(int N) { return N == 2 ? GPF_ZCHUNK_PHI2 : GPF_ZCHUNK_PHI; }
 // a k_mulbm_z block's planes lie within one k_phi_z block's (its bulk flag applies)
-static_assert(kZChunkPhi % kZChunkMu == 0, "the phase-field plane chunk must be a multiple of the LBM's");
-// blocks of one k_phi_z launch (64 x kTileY tiles, kZChunkPhi planes each in 3D)
+static_assert(zchunk_phi(2) % kZChunkMu == 0 && zchunk_phi(3) % kZChunkMu == 0,
+              "the phase-field plane chunk must be a multiple of the LBM's");
+// blocks of one k_phi_z launch (64 x kTileY tiles, zchunk_phi(N) planes each in 3D)
 inline int64_t phi_blocks(const gpf_ctx* c) {
   const int64_t tx = (c->n[0] + 63) / 64, ty = (c->n[1] + kTileY - 1) / kTileY;
-  const int64_t tz = (c->dim == 3) ? (c->n[2] + kZChunkPhi - 1) / kZChunkPhi : 1;
+  const int zc = zchunk_phi(c->N);
+  const int64_t tz = (c->dim == 3) ? (c->n[2] + zc - 1) / zc : 1;
   return tx * ty * tz;
 }
 
@@ -344,7 +354,7 @@ struct Impl {
   static void launch_step(gpf_ctx* c, const gpf::KP<R>& k, const SP& in, const SP& out, R ts,
                           hipStream_t st, hipEvent_t* ev, const uint8_t* bulk_in = nullptr,
                           uint8_t* bulk_out = nullptr, uint8_t* act_out = nullptr) {
-    constexpr int TX = 64, TY = kTileY;
+    constexpr int TX = 64, TY = kTileY, ZP = zchunk_phi(N);
     const int tiles_x = (int)((c->n[0] + TX - 1) / TX), tiles_y = (int)((c->n[1] + TY - 1) / TY);
     auto grid = [&](int zc) {
       const int tiles_z = (D == 3) ? (int)((c->n[2] + zc - 1) / zc) : 1;
@@ -353,15 +363,15 @@ struct Impl {
     const dim3 block(TX * TY);
     if (ev) (void)hipEventRecord(ev[0], st);
     if (act_out)
-      hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, true>), grid(kZChunkPhi), block, 0, st, k, in.phi,
-                         in.mu, out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, kZChunkPhi);
+      hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, true>), grid(ZP), block, 0, st, k, in.phi, in.mu,
+                         out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, ZP);
     else
-      hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, false>), grid(kZChunkPhi), block, 0, st, k, in.phi,
-                         in.mu, out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, kZChunkPhi);
+      hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, false>), grid(ZP), block, 0, st, k, in.phi, in.mu,
+                         out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, ZP);
     if (ev) (void)hipEventRecord(ev[1], st);
 #define GPF_MULBM(SH, MT)                                                                                     \
   hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, SH, MT>), grid(kZChunkMu), block, 0, st, k, in.phi, \
-                     out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, bulk_out, kZChunkPhi, ts, tiles_x,    \
+                     out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, bulk_out, ZP, ts, tiles_x,            \
                      tiles_y, kZChunkMu)
     if (k.shrink) {
       if (k.tdep)
