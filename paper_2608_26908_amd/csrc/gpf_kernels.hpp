@@ -559,11 +559,8 @@ struct Tile {
   int x0, y0, z0, z1;
   unsigned lb;  // logical tile index: x fastest, then y, then the chunk along z
 };
-__device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty, int zc, int nz,
-                                        int D) {
-  const unsigned nb = gridDim.x, b = blockIdx.x;
-  const unsigned per8 = nb / 8u;
-  const unsigned lb = (b < per8 * 8u) ? (b % 8u) * per8 + b / 8u : b;
+__device__ __forceinline__ Tile tile_at(unsigned lb, int tiles_x, int tiles_y, int tx, int ty, int zc,
+                                        int nz, int D) {
   Tile t;
   t.lb = lb;
   t.x0 = (int)(lb % (unsigned)tiles_x) * tx;
@@ -572,6 +569,13 @@ __device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty
   t.z0 = (D == 3) ? tz * zc : 0;
   t.z1 = (D == 3) ? min(t.z0 + zc, nz) : 1;
   return t;
+}
+__device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty, int zc, int nz,
+                                        int D) {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned per8 = nb / 8u;
+  const unsigned lb = (b < per8 * 8u) ? (b % 8u) * per8 + b / 8u : b;
+  return tile_at(lb, tiles_x, tiles_y, tx, ty, zc, nz, D);
 }
 
 // ---------------------------------------------------------------------------
@@ -583,62 +587,21 @@ __device__ __forceinline__ Tile tile_of(int tiles_x, int tiles_y, int tx, int ty
 // computed and stored to the ring after it, so its loads are in flight during
 // the computation; one barrier per plane.
 // ---------------------------------------------------------------------------
-template <int D, int N, int NC, class R, int TX, int TY, bool ACT>
-__global__ void __launch_bounds__(TX * TY)
-k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
-        const uint8_t* __restrict__ bulk_in, uint8_t* __restrict__ bulk_out, uint8_t* __restrict__ act_out,
-        R tshift, int tiles_x, int tiles_y, int zc) {
+// One block's walk through the planes of its tile T (the body of k_phi_z and
+// k_phi_zl).  was_bulk: phi_out, which still holds phi^{n-1}, already holds
+// phi^n on every cell of T.  Ends in a barrier after the last read of the
+// ring.
+template <int D, int N, int NC, class R, int TX, int TY, bool ACT, class Ring>
+__device__ __forceinline__ void phi_walk(const KP<R>& p, const R* __restrict__ phi, const R* __restrict__ mu,
+                                         R* __restrict__ phi_out, bool was_bulk, uint8_t* __restrict__ bulk_out,
+                                         uint8_t* __restrict__ act_out, R tshift, const Tile& T, Ring& ring) {
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
   constexpr int NT = TX * TY, PER = (HC + NT - 1) / NT;  // halo-tile cells per thread
-  constexpr int NS = (D == 3) ? 4 : 1;
-  __shared__ R ring[NS][N][HC];
-  const Tile T = tile_of(tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
   const int x = T.x0 + lx, y = T.y0 + ly;
   const bool own = x < p.n[0] && y < p.n[1];
   const int c0 = (ly + 1) * HX + (lx + 1);
-  // Bulk history (both null when phi_out is not the buffer that held phi^{n-1}),
-  // one flag per block (logical tile index): bulk_in[block] says every cell of
-  // this block's tile and planes was bulk in the step that produced phi^n from
-  // phi^{n-1}, so phi_out, which still holds phi^{n-1}, already holds phi^n
-  // there, and a cell that is bulk again (phi^{n+1} = phi^n) need not be
-  // stored.  bulk_out[block] records the same for this step.
-  // ACT (recomputation for the adjoint): act_out receives each cell's active
-  // set of phases, which the reverse of the step reads instead of phi^n's
-  // stencil (an instance of its own keeps the registers of the common case)
-  if (bulk_in && (D == 3 || p.cells > ((int64_t)1 << 18))) {
-    // If this block and every block its stencils reach (the 26 around it, none
-    // beyond a wall) were bulk in that step, phi^n = phi^{n-1} on every stencil
-    // the block evaluates, so each cell has its previous active set and is
-    // bulk again: phi_out already holds phi^{n+1} = phi^n, nothing to do.  (On
-    // small 2D grids, whose one-plane blocks make a launch of a few
-    // microseconds, the flag loads cost what they save.)
-    int ok = 1;
-    if (tid < 27) {
-      const int d[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
-      const int nt[3] = {tiles_x, tiles_y, (int)(gridDim.x / (unsigned)(tiles_x * tiles_y))};
-      int t3[3] = {(int)(T.lb % (unsigned)tiles_x), (int)((T.lb / (unsigned)tiles_x) % (unsigned)tiles_y),
-                   (int)(T.lb / (unsigned)(tiles_x * tiles_y))};
-      bool exists = true;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        t3[a] += d[a];
-        if (t3[a] < 0 || t3[a] >= nt[a]) {
-          if (a < D && p.per[a])
-            t3[a] += (t3[a] < 0) ? nt[a] : -nt[a];
-          else
-            exists = false;
-        }
-      }
-      if (exists) ok = bulk_in[t3[0] + tiles_x * (t3[1] + tiles_y * t3[2])];
-    }
-    if (__syncthreads_and(ok)) {
-      if (bulk_out && tid == 0) bulk_out[T.lb] = 1;
-      return;
-    }
-  }
-  const bool was_bulk = bulk_in && bulk_in[T.lb];
   int all_bulk = 1;
 
   // in-plane offsets of this thread's halo-tile cells (fixed along z)
@@ -728,6 +691,128 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
   record_bulk();
 }
 
+// Bulk flag of the tile at neighbour offset i (0..26: dx, dy, dz in -1..1,
+// x fastest) of logical tile lb in a grid of nt[0] x nt[1] x nt[2] tiles;
+// periodic axes wrap, and a tile beyond a wall counts as bulk (no stencil
+// reaches across a wall).
+__device__ __forceinline__ int bulk_flag_at(const uint8_t* __restrict__ bulk, unsigned lb, int i, const int nt[3],
+                                            const int per[3], int D) {
+  const int d[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
+  int t3[3] = {(int)(lb % (unsigned)nt[0]), (int)((lb / (unsigned)nt[0]) % (unsigned)nt[1]),
+               (int)(lb / (unsigned)(nt[0] * nt[1]))};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    t3[a] += d[a];
+    if (t3[a] < 0 || t3[a] >= nt[a]) {
+      if (a < D && per[a])
+        t3[a] += (t3[a] < 0) ? nt[a] : -nt[a];
+      else
+        return 1;
+    }
+  }
+  return bulk[t3[0] + nt[0] * (t3[1] + nt[1] * t3[2])];
+}
+
+template <int D, int N, int NC, class R, int TX, int TY, bool ACT>
+__global__ void __launch_bounds__(TX * TY)
+k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
+        const uint8_t* __restrict__ bulk_in, uint8_t* __restrict__ bulk_out, uint8_t* __restrict__ act_out,
+        R tshift, int tiles_x, int tiles_y, int zc) {
+  constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
+  constexpr int NS = (D == 3) ? 4 : 1;
+  __shared__ R ring[NS][N][HC];
+  const Tile T = tile_of(tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
+  const int tid = threadIdx.x;
+  // Bulk history (both null when phi_out is not the buffer that held phi^{n-1}),
+  // one flag per block (logical tile index): bulk_in[block] says every cell of
+  // this block's tile and planes was bulk in the step that produced phi^n from
+  // phi^{n-1}, so phi_out, which still holds phi^{n-1}, already holds phi^n
+  // there, and a cell that is bulk again (phi^{n+1} = phi^n) need not be
+  // stored.  bulk_out[block] records the same for this step.
+  // ACT (recomputation for the adjoint): act_out receives each cell's active
+  // set of phases, which the reverse of the step reads instead of phi^n's
+  // stencil (an instance of its own keeps the registers of the common case)
+  if (bulk_in && (D == 3 || p.cells > ((int64_t)1 << 18))) {
+    // If this block and every block its stencils reach (the 26 around it, none
+    // beyond a wall) were bulk in that step, phi^n = phi^{n-1} on every stencil
+    // the block evaluates, so each cell has its previous active set and is
+    // bulk again: phi_out already holds phi^{n+1} = phi^n, nothing to do.  (On
+    // small 2D grids, whose one-plane blocks make a launch of a few
+    // microseconds, the flag loads cost what they save.)
+    int ok = 1;
+    if (tid < 27) {
+      const int nt[3] = {tiles_x, tiles_y, (int)(gridDim.x / (unsigned)(tiles_x * tiles_y))};
+      ok = bulk_flag_at(bulk_in, T.lb, tid, nt, p.per, D);
+    }
+    if (__syncthreads_and(ok)) {
+      if (bulk_out && tid == 0) bulk_out[T.lb] = 1;
+      return;
+    }
+  }
+  phi_walk<D, N, NC, R, TX, TY, ACT>(p, phi, mu, phi_out, bulk_in && bulk_in[T.lb], bulk_out, act_out, tshift, T,
+                                     ring);
+}
+
+// ---------------------------------------------------------------------------
+// Phase field over a list of tiles (3D, bulk history on).  On a grid that is
+// mostly bulk nearly every block of a k_phi_z launch finds its neighbourhood
+// bulk and returns, yet the launch still pays the dispatch of all of them.
+// k_phi_todo checks every tile's neighbourhood, one thread per tile, sets the
+// flag of each tile it skips and appends the others to a list; k_phi_zl,
+// launched with a grid of resident blocks, walks the listed tiles.  Each XCD
+// walks a contiguous part of the list (whose waves append in about the order
+// of the tiles), so tiles that are neighbours share its L2 as in k_phi_z.
+// count is the length of the list; it starts at zero, and the step's
+// k_mulbm_z, which runs after k_phi_zl, clears it for the next step.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256)
+k_phi_todo(const uint8_t* __restrict__ bulk_in, uint8_t* __restrict__ bulk_out, unsigned* __restrict__ list,
+           unsigned* __restrict__ count, int tiles_x, int tiles_y, int tiles_z, int per0, int per1, int per2) {
+  const unsigned nb = (unsigned)tiles_x * (unsigned)tiles_y * (unsigned)tiles_z;
+  const unsigned lb = blockIdx.x * 256u + threadIdx.x;
+  bool need = false;
+  if (lb < nb) {
+    const int nt[3] = {tiles_x, tiles_y, tiles_z}, per[3] = {per0, per1, per2};
+    int ok = 1;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) ok &= bulk_flag_at(bulk_in, lb, i, nt, per, D);
+    if (ok)
+      bulk_out[lb] = 1;
+    else
+      need = true;
+  }
+  // one atomic per wave; the wave's listed tiles take consecutive slots
+  const unsigned long long m = __ballot(need);
+  const unsigned lane = __lane_id();
+  unsigned base = 0;
+  if (m && lane == 0) base = atomicAdd(count, (unsigned)__popcll(m));
+  base = __shfl(base, 0);
+  const unsigned slot = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+  if (need && slot < nb) list[slot] = lb;
+}
+
+template <int D, int N, int NC, class R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_phi_zl(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restrict__ phi_out,
+         const uint8_t* __restrict__ bulk_in, uint8_t* __restrict__ bulk_out, const unsigned* __restrict__ list,
+         const unsigned* __restrict__ count, R tshift, int tiles_x, int tiles_y, int zc) {
+  constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
+  __shared__ R ring[4][N][HC];
+  const unsigned nb = (unsigned)tiles_x * (unsigned)tiles_y * (unsigned)((p.n[2] + zc - 1) / zc);
+  const unsigned cnt = min(*count, nb);
+  // gridDim.x is a multiple of 8: XCD k (blocks b = k mod 8) takes part k of the list
+  const unsigned g8 = gridDim.x / 8u, k = blockIdx.x % 8u;
+  const unsigned hi = (unsigned)(((unsigned long long)cnt * (k + 1u)) / 8u);
+  for (unsigned w = (unsigned)(((unsigned long long)cnt * k) / 8u) + blockIdx.x / 8u; w < hi; w += g8) {
+    const unsigned lb = list[w];
+    if (lb >= nb) continue;  // never written (the list starts zeroed): the same for the whole block
+    const Tile T = tile_at(lb, tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
+    phi_walk<D, N, NC, R, TX, TY, false>(p, phi, mu, phi_out, bulk_in[T.lb] != 0, bulk_out, nullptr, tshift, T,
+                                         ring);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Chemical potential + LBM, z-marching.  Each thread walks its (x, y) column
 // along z: phi^{n+1}, mu^n and U_z^{n-1} of the planes z-1, z, z+1 at its own
@@ -747,7 +832,8 @@ __global__ void __launch_bounds__(TX * TY)
 k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
           const R* __restrict__ mu, const R* __restrict__ uold, const R* __restrict__ fin,
           R* __restrict__ mu_out, R* __restrict__ u_out, R* __restrict__ fout, R* __restrict__ dr_out,
-          const uint8_t* __restrict__ phi_bulk, int zc_phi, R tshift, int tiles_x, int tiles_y, int zc) {
+          const uint8_t* __restrict__ phi_bulk, int zc_phi, R tshift, int tiles_x, int tiles_y, int zc,
+          unsigned* __restrict__ todo_count) {
   static_assert(TX == 64, "one tile row per 64-lane wave");
   static_assert(TY >= 2, "edge threads own one row and one column halo cell at most");
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
@@ -756,6 +842,9 @@ k_mulbm_z(KP<R> p, const R* __restrict__ phi0, const R* __restrict__ phi1,
   __shared__ R sh[NB][NV][HC];
   const Tile T = tile_of(tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
   const int tid = threadIdx.x;
+  // the step's k_phi_zl, which read the list length, has finished: clear it
+  // for the next step's k_phi_todo
+  if (todo_count && blockIdx.x == 0 && tid == 0) atomicExch(todo_count, 0u);
   const int lx = tid % TX, ly = __builtin_amdgcn_readfirstlane(tid / TX);
   const int x = T.x0 + lx, y = T.y0 + ly;
   const bool own = x < p.n[0] && y < p.n[1];

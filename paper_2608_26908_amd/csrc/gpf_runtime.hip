@@ -63,6 +63,11 @@ struct gpf_ctx {
   // unchanged on the block's cells (valid while bulk_ok[i])
   DevBuf bulkf[2];
   bool bulk_ok[2] = {false, false};
+  // tiles that k_phi_zl walks (3D, two phases, bulk history on) and their
+  // number, which starts at zero; zl_grid: its blocks per launch, the
+  // device's resident blocks of it
+  DevBuf tlist, tcount;
+  unsigned zl_grid = 0;
   int64_t frame_off = 0;  // moving frame: cells shifted so far along the pull axis
   const double* target = nullptr;  // loss target (caller's device memory, N * cells FP64)
   int device = 0;                    // HIP device current at gpf_init
@@ -301,7 +306,7 @@ inline unsigned adj_blocks(const int64_t (&n)[3]) {
 #define GPF_TILE_Y 4
 #endif
 #ifndef GPF_ZCHUNK_PHI2
-#define GPF_ZCHUNK_PHI2 8
+#define GPF_ZCHUNK_PHI2 4
 #endif
 #ifndef GPF_ZCHUNK_PHI
 #define GPF_ZCHUNK_PHI 16
@@ -310,10 +315,11 @@ inline unsigned adj_blocks(const int64_t (&n)[3]) {
 #define GPF_ZCHUNK_MU 4
 #endif
 constexpr int kTileY = GPF_TILE_Y, kZChunkMu = GPF_ZCHUNK_MU;
-// planes per k_phi_z block: two phases spend most of a step in the few blocks
-// that hold the interface, whose plane walk a shorter chunk shortens; three
-// and four phases have interface throughout the solid, where a longer chunk
-// re-reads fewer halo planes
+// planes per phase-field block: a two-phase step spends its phase-field time
+// in the few tiles near the interface (3D: the listed tiles of k_phi_zl),
+// whose plane walk a shorter chunk shortens; three and four phases have
+// interface throughout the solid, where a longer chunk re-reads fewer halo
+// planes
 constexpr int zchunk_phi(int N) { return N == 2 ? GPF_ZCHUNK_PHI2 : GPF_ZCHUNK_PHI; }
 // a k_mulbm_z block's planes lie within one k_phi_z block's (its bulk flag applies)
 static_assert(zchunk_phi(2) % kZChunkMu == 0 && zchunk_phi(3) % kZChunkMu == 0,
@@ -362,17 +368,34 @@ struct Impl {
     };
     const dim3 block(TX * TY);
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (act_out)
-      hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, true>), grid(ZP), block, 0, st, k, in.phi, in.mu,
-                         out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, ZP);
-    else
-      hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, false>), grid(ZP), block, 0, st, k, in.phi, in.mu,
-                         out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, ZP);
+    unsigned* counts = nullptr;  // set when the listed phase-field kernels ran
+    if constexpr (D == 3 && N == 2) {
+      if (bulk_in && !act_out && c->zl_grid) {
+        // the tiles whose neighbourhood changed, then a walk over them only
+        const int tiles_z = (int)((c->n[2] + ZP - 1) / ZP);
+        const unsigned nb = (unsigned)tiles_x * (unsigned)tiles_y * (unsigned)tiles_z;
+        unsigned* list = static_cast<unsigned*>(c->tlist.ptr);
+        counts = static_cast<unsigned*>(c->tcount.ptr);
+        hipLaunchKernelGGL((gpf::k_phi_todo<D>), dim3((nb + 255u) / 256u), dim3(256), 0, st, bulk_in, bulk_out, list,
+                           counts, tiles_x, tiles_y, tiles_z, k.per[0], k.per[1], k.per[2]);
+        const unsigned g = std::max(8u, std::min(c->zl_grid, (nb + 7u) / 8u * 8u));
+        hipLaunchKernelGGL((gpf::k_phi_zl<D, N, NC, R, TX, TY>), dim3(g), block, 0, st, k, in.phi, in.mu, out.phi,
+                           bulk_in, bulk_out, list, counts, ts, tiles_x, tiles_y, ZP);
+      }
+    }
+    if (!counts) {
+      if (act_out)
+        hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, true>), grid(ZP), block, 0, st, k, in.phi, in.mu,
+                           out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, ZP);
+      else
+        hipLaunchKernelGGL((gpf::k_phi_z<D, N, NC, R, TX, TY, false>), grid(ZP), block, 0, st, k, in.phi, in.mu,
+                           out.phi, bulk_in, bulk_out, act_out, ts, tiles_x, tiles_y, ZP);
+    }
     if (ev) (void)hipEventRecord(ev[1], st);
 #define GPF_MULBM(SH, MT)                                                                                     \
   hipLaunchKernelGGL((gpf::k_mulbm_z<D, Q, N, NC, R, TX, TY, SH, MT>), grid(kZChunkMu), block, 0, st, k, in.phi, \
                      out.phi, in.mu, in.u, in.f, out.mu, out.u, out.f, out.dr, bulk_out, ZP, ts, tiles_x,            \
-                     tiles_y, kZChunkMu)
+                     tiles_y, kZChunkMu, counts)
     if (k.shrink) {
       if (k.tdep)
         GPF_MULBM(true, true);
@@ -484,6 +507,15 @@ struct Impl {
 
   static int step(gpf_ctx* c, int64_t nsteps, double* kernel_ms, int nk) {
     gpf::KP<R> k = make_kp<R>(c);
+    if constexpr (D == 3 && N == 2) {
+      if (!c->zl_grid) {  // once, outside any capture: k_phi_zl's grid (a multiple of 8)
+        int per_cu = 0, cus = 0;
+        HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &per_cu, gpf::k_phi_zl<D, N, NC, R, 64, kTileY>, 64 * kTileY, 0));
+        HIP_OR_FAIL(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->zl_grid = std::max(8u, (unsigned)(std::max(per_cu, 1) * cus) / 8u * 8u);
+      }
+    }
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (kernel_ms) {
       for (int i = 0; i < 3; ++i) HIP_OR_FAIL(c, hipEventCreate(&ev[i]));
@@ -1222,6 +1254,8 @@ void free_all(gpf_ctx* c) {
   dev_release(c, c->frontbuf);
   dev_release(c, c->bulkf[0]);
   dev_release(c, c->bulkf[1]);
+  dev_release(c, c->tlist);
+  dev_release(c, c->tcount);
   auto rel = [&](StateBuf& s) {
     dev_release(c, s.phi);
     dev_release(c, s.mu);
@@ -1336,8 +1370,12 @@ int gpf_init(gpf_ctx** out, const gpf_grid* grid, int32_t n_phases, int32_t n_co
   if (!rc) rc = dev_alloc(c, c->badstep, sizeof(unsigned long long));
   if (!rc) rc = dev_alloc(c, c->frontbuf, sizeof(int));
   for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(c, c->bulkf[i], (size_t)phi_blocks(c));
+  if (!rc) rc = dev_alloc(c, c->tlist, (size_t)phi_blocks(c) * sizeof(unsigned));
+  if (!rc) rc = dev_alloc(c, c->tcount, sizeof(unsigned));
   if (!rc) {
     hipError_t e = hipMemsetAsync(c->badstep.ptr, 0xff, sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->tcount.ptr, 0, sizeof(unsigned), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->tlist.ptr, 0, c->tlist.bytes, c->stream);
     if (e != hipSuccess) rc = fail(c, GPF_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
   }
   if (!rc) rc = init_state(c, seed);
