@@ -754,9 +754,10 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Phase field over a list of tiles (3D, bulk history on).  On a grid that is
-// mostly bulk nearly every block of a k_phi_z launch finds its neighbourhood
-// bulk and returns, yet the launch still pays the dispatch of all of them.
+// Phase field over a list of tiles (3D two-phase grids with the bulk history
+// on).  On a grid that is mostly bulk nearly every block of a k_phi_z launch
+// finds its neighbourhood bulk and returns, yet the launch still pays the
+// dispatch of all of them.
 // k_phi_todo checks every tile's neighbourhood, one thread per tile, sets the
 // flag of each tile it skips and appends the others to a list; k_phi_zl,
 // launched with a grid of resident blocks, walks the listed tiles.  Each XCD
@@ -806,7 +807,9 @@ k_phi_zl(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __rest
   const unsigned hi = (unsigned)(((unsigned long long)cnt * (k + 1u)) / 8u);
   for (unsigned w = (unsigned)(((unsigned long long)cnt * k) / 8u) + blockIdx.x / 8u; w < hi; w += g8) {
     const unsigned lb = list[w];
-    if (lb >= nb) continue;  // never written (the list starts zeroed): the same for the whole block
+    // entries are tile indices (the list starts zeroed); the check keeps a
+    // count that disagrees with the list inside the grid (uniform per block)
+    if (lb >= nb) continue;
     const Tile T = tile_at(lb, tiles_x, tiles_y, TX, TY, zc, p.n[2], D);
     phi_walk<D, N, NC, R, TX, TY, false>(p, phi, mu, phi_out, bulk_in[T.lb] != 0, bulk_out, nullptr, tshift, T,
                                          ring);
