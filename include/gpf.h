@@ -179,9 +179,9 @@ int gpf_step(gpf_ctx* ctx, int64_t n);
 /* Like gpf_step (Algorithm phfLBM, App. A), and records HIP events around
  * each part of the step on the context's stream; kernel_ms[j] receives the
  * summed milliseconds of part j (j = 0: phase field, one kernel, or on 3D
- * two-phase grids with the bulk history the tile check and the walk of the
- * listed tiles together; 1: chemical potential + LBM), count up to
- * n_kernels.  Synchronises.  For measurement only. */
+ * grids with the bulk history the tile check and the walk of the listed
+ * tiles together; 1: chemical potential + LBM), count up to n_kernels.
+ * Synchronises.  For measurement only. */
 int gpf_step_timed(gpf_ctx* ctx, int64_t n, double* kernel_ms, int32_t n_kernels);
 
 /* Copy a field to caller-owned host memory as FP64 (adds w_k rho0 back to f

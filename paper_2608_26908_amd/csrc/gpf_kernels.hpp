@@ -754,10 +754,10 @@ k_phi_z(KP<R> p, const R* __restrict__ phi, const R* __restrict__ mu, R* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Phase field over a list of tiles (3D two-phase grids with the bulk history
-// on).  On a grid that is mostly bulk nearly every block of a k_phi_z launch
-// finds its neighbourhood bulk and returns, yet the launch still pays the
-// dispatch of all of them.
+// Phase field over a list of tiles (3D grids with the bulk history on).  On a
+// grid that is mostly bulk nearly every block of a k_phi_z launch finds its
+// neighbourhood bulk and returns, yet the launch still pays the dispatch of
+// all of them.
 // k_phi_todo checks every tile's neighbourhood, one thread per tile, sets the
 // flag of each tile it skips and appends the others to a list; k_phi_zl,
 // launched with a grid of resident blocks, walks the listed tiles.  Each XCD

@@ -63,7 +63,7 @@ struct gpf_ctx {
   // unchanged on the block's cells (valid while bulk_ok[i])
   DevBuf bulkf[2];
   bool bulk_ok[2] = {false, false};
-  // tiles that k_phi_zl walks (3D, two phases, bulk history on) and their
+  // tiles that k_phi_zl walks (3D grids, bulk history on) and their
   // number, which starts at zero; zl_grid: its blocks per launch, the
   // device's resident blocks of it
   DevBuf tlist, tcount;
@@ -316,10 +316,9 @@ inline unsigned adj_blocks(const int64_t (&n)[3]) {
 #endif
 constexpr int kTileY = GPF_TILE_Y, kZChunkMu = GPF_ZCHUNK_MU;
 // planes per phase-field block: a two-phase step spends its phase-field time
-// in the few tiles near the interface (3D: the listed tiles of k_phi_zl),
-// whose plane walk a shorter chunk shortens; three and four phases have
-// interface throughout the solid, where a longer chunk re-reads fewer halo
-// planes
+// in the few tiles near the interface (3D: the tiles k_phi_zl walks), whose
+// plane walk a shorter chunk shortens; three and four phases have interface
+// throughout the solid, where a longer chunk re-reads fewer halo planes
 constexpr int zchunk_phi(int N) { return N == 2 ? GPF_ZCHUNK_PHI2 : GPF_ZCHUNK_PHI; }
 // a k_mulbm_z block's planes lie within one k_phi_z block's (its bulk flag applies)
 static_assert(zchunk_phi(2) % kZChunkMu == 0 && zchunk_phi(3) % kZChunkMu == 0,
@@ -369,7 +368,7 @@ struct Impl {
     const dim3 block(TX * TY);
     if (ev) (void)hipEventRecord(ev[0], st);
     unsigned* counts = nullptr;  // set when the listed phase-field kernels ran
-    if constexpr (D == 3 && N == 2) {
+    if constexpr (D == 3) {
       if (bulk_in && !act_out && c->zl_grid) {
         // the tiles whose neighbourhood changed, then a walk over them only
         const int tiles_z = (int)((c->n[2] + ZP - 1) / ZP);
@@ -507,7 +506,7 @@ struct Impl {
 
   static int step(gpf_ctx* c, int64_t nsteps, double* kernel_ms, int nk) {
     gpf::KP<R> k = make_kp<R>(c);
-    if constexpr (D == 3 && N == 2) {
+    if constexpr (D == 3) {
       if (!c->zl_grid) {  // once, outside any capture: k_phi_zl's grid (a multiple of 8)
         int per_cu = 0, cus = 0;
         HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(

@@ -198,16 +198,20 @@ def test_written_state_is_stepped_in_full():
     # every axis periodic, a ragged last chunk along z (50 planes), the seed
     # across the periodic faces: wrapped neighbour tiles in the skip decision
     ("dendrite3d", [64, 64, 50], dict(periodic=[1, 1, 1], init_center=[1.0, 62.0, 48.5])),
+    # three phases, two solutes, compositions depending on T: lamellae below
+    # the melt, whose tiles the list leaves out
+    ("eutectic3d", [64, 48, 96], {}),
     ("eutectic2d", [1024, 512], {})])
 def test_bulk_history_skip_is_bitwise(name, n, over):
     """A tile is skipped outright when it and every tile its stencils reach
     were bulk in the step before (3D, and 2D grids above 2^18 cells); on 3D
-    two-phase grids k_phi_todo lists the other tiles and k_phi_zl walks them.
+    grids k_phi_todo lists the other tiles and k_phi_zl walks them.
     Stepping with that history must give bit for bit the state of stepping
     with the history voided after every step (a write of the same state), here
     while the dendrite's interface crosses tile boundaries (64 x 4 tiles, 4
-    planes), also across periodic faces, and on the eutectic's moving front."""
-    cfg = scaled(name, n, **over) if name == "dendrite3d" else workload(name)
+    planes), also across periodic faces, on 3D lamellae (16 planes) and on the
+    2D eutectic's moving front."""
+    cfg = scaled(name, n, **over) if name.endswith("3d") else workload(name)
     a = _sim(cfg, "fp32")
     b = _sim(cfg, "fp32")
     steps = 150 if name == "dendrite3d" else 120
